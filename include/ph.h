@@ -1,0 +1,171 @@
+/*
+ * ph.h - C ABI of libpairhmm: the Pair-HMM forward algorithm and its adjoint
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (arXiv 2411.11547, Section II-A): for a read R = r_1..r_m
+ * and a haplotype H = h_1..h_n over {A,C,G,T,N}, the match/insert/delete
+ * recurrences Eq. (1)-(3) with emissions Eq. (4), initialised with
+ * M(i,0) = I(i,0) = D(i,0) = 0, M(0,j) = I(0,j) = 0, D(0,j) = 1/n, give the
+ * likelihood L = sum_{j=1..n} (M(m,j) + I(m,j)).  Every call returns
+ * log10 L for every read/haplotype pair of a list of batches
+ * B_q = (R_q, H_q) (Section II-A, last paragraph; Section III-A).
+ *
+ * Conventions fixed by this library where the paper leaves them open:
+ *  - Phred decoding per read position: Q = 10^(-q/10) for the base quality,
+ *    delta = 10^(-ins/10), zeta = 10^(-del/10), eps = 10^(-gcp/10),
+ *    alpha = 1 - delta - zeta, beta = 1 - eps, lam_match = 1 - Q,
+ *    lam_mismatch = Q / 3.
+ *  - Base codes: A=0, C=1, G=2, T=3, N=4; N on either side is a match.
+ *  - D(0,0) = 1/n (the zero initialisation covers rows i >= 1 only).
+ *
+ * Memory: unless stated otherwise every pointer is DEVICE memory (hipMalloc
+ * or torch CUDA tensors), owned by the caller, and must stay valid until the
+ * work enqueued on `stream` has completed.  The plan owns its scratch.
+ *
+ * Streams: calls enqueue work on `stream` (a hipStream_t; NULL = the null
+ * stream) and return without waiting; results are valid once the stream has
+ * been synchronised.  A plan must not be used from two streams at once.
+ *
+ * Errors: every function returns a ph_status and never aborts or throws.
+ * ph_last_error() returns a message for the most recent failure of the
+ * calling thread.
+ */
+#ifndef PH_H
+#define PH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PH_OK = 0,
+    PH_ERR_INVALID = -1,       /* bad argument: NULL pointer, empty read or haplotype, bad code */
+    PH_ERR_UNSUPPORTED = -2,   /* read longer than the longest compiled kernel configuration */
+    PH_ERR_NOMEM = -3,         /* device or host allocation failed */
+    PH_ERR_HIP = -4,           /* a HIP runtime call failed; see ph_last_error() */
+    PH_ERR_PLAN_MISMATCH = -5, /* the problem does not have the shape the plan was built for */
+    PH_ERR_STATE = -6          /* call order violated (e.g. backward without a checkpointed forward) */
+} ph_status;
+
+/* Per-pair status written next to each score. */
+enum {
+    PH_PAIR_FP32 = 0,           /* FP32 sweep, scaled sum above the underflow threshold */
+    PH_PAIR_FP64 = 1,           /* recomputed by the FP64 sweep */
+    PH_PAIR_FP64_FLOOR = 2,     /* FP64 sweep, but below its own range floor: unreliable */
+    PH_PAIR_FP32_UNRESCUED = 3  /* FP32 below threshold in a mode without rescue */
+};
+
+/* Shape of a problem: batch structure and sequence lengths, HOST memory.
+ * Reads of batch q are batch_read_begin[q] .. batch_read_begin[q+1]-1, its
+ * haplotypes batch_hap_begin[q] .. batch_hap_begin[q+1]-1; read r spans
+ * read_offset[r] .. read_offset[r+1]-1 of the per-base arrays, haplotype h
+ * spans hap_offset[h] .. hap_offset[h+1]-1 of hap_bases. */
+typedef struct {
+    int32_t num_batches;
+    const int32_t *batch_read_begin; /* [num_batches + 1], non-decreasing, starts at 0 */
+    const int32_t *batch_hap_begin;  /* [num_batches + 1], non-decreasing, starts at 0 */
+    int32_t num_reads;
+    const int64_t *read_offset;      /* [num_reads + 1] */
+    int32_t num_haps;
+    const int64_t *hap_offset;       /* [num_haps + 1] */
+} ph_shape;
+
+/* The data of a problem, DEVICE memory, same structure as ph_shape.  The
+ * CSR arrays must hold the values the plan was built from. */
+typedef struct {
+    int32_t num_batches;
+    const int32_t *batch_read_begin; /* [num_batches + 1] */
+    const int32_t *batch_hap_begin;  /* [num_batches + 1] */
+    int32_t num_reads;
+    const int64_t *read_offset;      /* [num_reads + 1] */
+    const uint8_t *read_bases;       /* [read_offset[num_reads]] codes 0..4 */
+    const uint8_t *base_qual;        /* Phred per read base */
+    const uint8_t *ins_qual;         /* Phred of an insertion starting after this base */
+    const uint8_t *del_qual;         /* Phred of a deletion starting after this base */
+    const uint8_t *gcp_qual;         /* Phred of gap continuation */
+    int32_t num_haps;
+    const int64_t *hap_offset;       /* [num_haps + 1] */
+    const uint8_t *hap_bases;        /* [hap_offset[num_haps]] codes 0..4 */
+} ph_problem;
+
+typedef struct {
+    /* Scaled FP32 row-m sum below which a pair is recomputed in FP64.
+     * The FP32 sweep starts from D(0,j) = 2^120 / n, so the default 1e-28
+     * corresponds to log10 L of about -64.1.  <= 0 selects the default;
+     * +inf sends every pair to the FP64 sweep. */
+    double rescue_threshold;
+    int use_graph;         /* 1: capture the launch sequence once and replay it */
+    int plain;             /* 1: one FP32 kernel sized for the longest read, pairs
+                              in output order, no binning, no rescue (baseline) */
+    int force_p;           /* 0 = tuned; else lanes per pair (16, 32 or 64) for every bin */
+    int keep_checkpoints;  /* 1: forward stores what ph_backward_batch needs */
+    const char *tune_table_path; /* NULL = built-in table; else a text file of
+                                    "max_read_len lanes rows_per_lane" lines */
+} ph_plan_opts;
+
+typedef struct ph_plan ph_plan; /* opaque: owns scratch, queues, checkpoints, graph */
+
+/* Fill opts with defaults. */
+void ph_plan_opts_default(ph_plan_opts *opts);
+
+/* Build a plan for problems of the given shape (HOST arrays, read once).
+ * Validates the shape: batch ranges inside the read/haplotype counts, every
+ * read and haplotype non-empty (PH_ERR_INVALID), every read within the
+ * compiled range (PH_ERR_UNSUPPORTED); then sizes and allocates device
+ * scratch on the current device.  *out receives the plan. */
+ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts, ph_plan **out);
+
+/* Number of pairs P = sum_q |R_q| |H_q| and real cells sum_pairs m*n. */
+ph_status ph_plan_info(const ph_plan *plan, int64_t *num_pairs, int64_t *num_cells,
+                       int32_t *max_read_len, int32_t *max_hap_len);
+
+/* Forward pass (Section III-B): out_log10L[P] (device, double) receives
+ * log10 L of every pair, in batch-major, read, haplotype order;
+ * out_status[P] (device, uint8, may be NULL) the per-pair ph status.
+ * log10_params: NULL to derive parameters from the Phred arrays, else a
+ * device float array [read_offset[num_reads]][7] of log10 probabilities
+ * {alpha, beta, delta, eps, zeta, lam_match, lam_mismatch} per read base.
+ * The problem's counts must equal the plan's (PH_ERR_PLAN_MISMATCH). */
+ph_status ph_forward_batch(ph_plan *plan, const ph_problem *problem,
+                           const float *log10_params, double *out_log10L,
+                           uint8_t *out_status, void *stream);
+
+/* Adjoint pass: grad_params[read_offset[num_reads]][7] (device, float)
+ * receives d(sum_p u_p log10 L_p)/d log10 theta for the seven parameters of
+ * every read base, u = grad_log10L[P] (device, double).  Requires a preceding
+ * ph_forward_batch on the same plan, problem and parameters, with
+ * keep_checkpoints set (PH_ERR_STATE otherwise).  The gradient buffer is
+ * overwritten, not accumulated into. */
+ph_status ph_backward_batch(ph_plan *plan, const ph_problem *problem,
+                            const float *log10_params, const double *grad_log10L,
+                            float *grad_params, void *stream);
+
+/* Check the device data of a problem against the plan: every base code in
+ * 0..4.  Synchronous; PH_ERR_INVALID if a code is out of range.  The forward
+ * pass itself does not read-validate device data. */
+ph_status ph_validate(ph_plan *plan, const ph_problem *problem, void *stream);
+
+/* Kernel-level timing of the most recent ph_forward_batch / ph_backward_batch
+ * on this plan, from HIP events recorded on the call's stream around each
+ * stage.  ms[0] = binning, ms[1] = FP32 sweep, ms[2] = FP64 rescue,
+ * ms[3] = adjoint sweep.  Synchronises the stream. */
+ph_status ph_plan_stage_ms(ph_plan *plan, float ms[4]);
+
+/* Number of pairs sent to the FP64 sweep by the most recent forward call
+ * (synchronises the stream). */
+ph_status ph_plan_rescued(ph_plan *plan, int64_t *count);
+
+void ph_plan_destroy(ph_plan *plan);
+
+/* Message of the calling thread's most recent failure ("" if none). */
+const char *ph_last_error(void);
+
+/* Library version string. */
+const char *ph_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PH_H */

@@ -1,0 +1,245 @@
+"""ctypes binding of libpairhmm (include/ph.h): argument marshalling only.
+
+Every step of the Pair-HMM path runs in the HIP kernels behind the C ABI;
+this module converts arrays to device tensors (torch is used for device
+memory and streams only), fills the C structs and calls the entry points of
+the same names.  There is no CPU fallback: if the library is missing or the
+GPU is unavailable, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpairhmm.so")
+
+PH_OK = 0
+STATUS_NAMES = {0: "PH_OK", -1: "PH_ERR_INVALID", -2: "PH_ERR_UNSUPPORTED", -3: "PH_ERR_NOMEM",
+                -4: "PH_ERR_HIP", -5: "PH_ERR_PLAN_MISMATCH", -6: "PH_ERR_STATE"}
+PAIR_FP32, PAIR_FP64, PAIR_FP64_FLOOR, PAIR_FP32_UNRESCUED = 0, 1, 2, 3
+
+EXPORTS = ("ph_plan_opts_default", "ph_plan_create", "ph_plan_info", "ph_forward_batch",
+           "ph_backward_batch", "ph_validate", "ph_plan_stage_ms", "ph_plan_rescued",
+           "ph_plan_destroy", "ph_last_error", "ph_version")
+
+_p = ctypes.c_void_p
+
+
+class PhShape(ctypes.Structure):
+    _fields_ = [("num_batches", ctypes.c_int32), ("batch_read_begin", _p), ("batch_hap_begin", _p),
+                ("num_reads", ctypes.c_int32), ("read_offset", _p),
+                ("num_haps", ctypes.c_int32), ("hap_offset", _p)]
+
+
+class PhProblem(ctypes.Structure):
+    _fields_ = [("num_batches", ctypes.c_int32), ("batch_read_begin", _p), ("batch_hap_begin", _p),
+                ("num_reads", ctypes.c_int32), ("read_offset", _p), ("read_bases", _p),
+                ("base_qual", _p), ("ins_qual", _p), ("del_qual", _p), ("gcp_qual", _p),
+                ("num_haps", ctypes.c_int32), ("hap_offset", _p), ("hap_bases", _p)]
+
+
+class PhPlanOpts(ctypes.Structure):
+    _fields_ = [("rescue_threshold", ctypes.c_double), ("use_graph", ctypes.c_int),
+                ("plain", ctypes.c_int), ("force_p", ctypes.c_int),
+                ("keep_checkpoints", ctypes.c_int), ("tune_table_path", ctypes.c_char_p)]
+
+
+class PHError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libpairhmm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2411_11547_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.ph_plan_opts_default.argtypes = [ctypes.POINTER(PhPlanOpts)]
+    lib.ph_plan_opts_default.restype = None
+    lib.ph_plan_create.argtypes = [ctypes.POINTER(PhShape), ctypes.POINTER(PhPlanOpts), ctypes.POINTER(P)]
+    lib.ph_plan_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.ph_forward_batch.argtypes = [P, ctypes.POINTER(PhProblem), P, P, P, P]
+    lib.ph_backward_batch.argtypes = [P, ctypes.POINTER(PhProblem), P, P, P, P]
+    lib.ph_validate.argtypes = [P, ctypes.POINTER(PhProblem), P]
+    lib.ph_plan_stage_ms.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
+    lib.ph_plan_rescued.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.ph_plan_destroy.argtypes = [P]
+    lib.ph_plan_destroy.restype = None
+    lib.ph_last_error.restype = ctypes.c_char_p
+    lib.ph_last_error.argtypes = []
+    lib.ph_version.restype = ctypes.c_char_p
+    lib.ph_version.argtypes = []
+    for name in ("ph_plan_create", "ph_plan_info", "ph_forward_batch", "ph_backward_batch",
+                 "ph_validate", "ph_plan_stage_ms", "ph_plan_rescued"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != PH_OK:
+        raise PHError(status, load().ph_last_error().decode())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _torch():
+    import torch  # device memory and streams only
+    return torch
+
+
+def current_stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class DeviceProblem:
+    """The arrays of a `workloads.Problem` as device tensors plus the C struct."""
+
+    FIELDS = ("batch_read_begin", "batch_hap_begin", "read_offset", "read_bases", "base_qual",
+              "ins_qual", "del_qual", "gcp_qual", "hap_offset", "hap_bases")
+
+    def __init__(self, problem, device="cuda"):
+        torch = _torch()
+        self.problem = problem
+        self.t = {}
+        for f in self.FIELDS:
+            arr = np.ascontiguousarray(getattr(problem, f))
+            if arr.size == 0:
+                arr = np.zeros(1, dtype=arr.dtype)  # keep a valid device pointer
+            self.t[f] = torch.from_numpy(arr).to(device)
+        self.c = PhProblem(problem.num_batches, *[self._ptr(f) for f in ("batch_read_begin", "batch_hap_begin")],
+                           problem.num_reads, *[self._ptr(f) for f in ("read_offset", "read_bases", "base_qual",
+                                                                       "ins_qual", "del_qual", "gcp_qual")],
+                           problem.num_haps, self._ptr("hap_offset"), self._ptr("hap_bases"))
+
+    def _ptr(self, f):
+        return ctypes.c_void_p(self.t[f].data_ptr())
+
+
+def shape_of(problem):
+    """PhShape over host arrays of a workloads.Problem (kept alive by the caller)."""
+    keep = [np.ascontiguousarray(problem.batch_read_begin, np.int32),
+            np.ascontiguousarray(problem.batch_hap_begin, np.int32),
+            np.ascontiguousarray(problem.read_offset, np.int64),
+            np.ascontiguousarray(problem.hap_offset, np.int64)]
+    s = PhShape(problem.num_batches, _np_ptr(keep[0]), _np_ptr(keep[1]), problem.num_reads,
+                _np_ptr(keep[2]), problem.num_haps, _np_ptr(keep[3]))
+    return s, keep
+
+
+# --- C ABI entry points (same names) -----------------------------------------
+def ph_plan_opts_default() -> PhPlanOpts:
+    o = PhPlanOpts()
+    load().ph_plan_opts_default(ctypes.byref(o))
+    return o
+
+
+def ph_plan_create(shape: PhShape, opts: PhPlanOpts) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(load().ph_plan_create(ctypes.byref(shape), ctypes.byref(opts), ctypes.byref(h)))
+    return h
+
+
+def ph_plan_info(plan):
+    P, C = ctypes.c_int64(), ctypes.c_int64()
+    M, Nn = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().ph_plan_info(plan, ctypes.byref(P), ctypes.byref(C), ctypes.byref(M), ctypes.byref(Nn)))
+    return P.value, C.value, M.value, Nn.value
+
+
+def ph_forward_batch(plan, problem: PhProblem, log10_params, out_log10L, out_status, stream):
+    _check(load().ph_forward_batch(plan, ctypes.byref(problem), log10_params, out_log10L, out_status, stream))
+
+
+def ph_backward_batch(plan, problem: PhProblem, log10_params, grad_log10L, grad_params, stream):
+    _check(load().ph_backward_batch(plan, ctypes.byref(problem), log10_params, grad_log10L, grad_params, stream))
+
+
+def ph_validate(plan, problem: PhProblem, stream):
+    _check(load().ph_validate(plan, ctypes.byref(problem), stream))
+
+
+def ph_plan_stage_ms(plan):
+    ms = (ctypes.c_float * 4)()
+    _check(load().ph_plan_stage_ms(plan, ms))
+    return list(ms)
+
+
+def ph_plan_rescued(plan) -> int:
+    c = ctypes.c_int64()
+    _check(load().ph_plan_rescued(plan, ctypes.byref(c)))
+    return c.value
+
+
+def ph_plan_destroy(plan):
+    load().ph_plan_destroy(plan)
+
+
+def ph_version() -> str:
+    return load().ph_version().decode()
+
+
+# --- convenience wrapper --------------------------------------------------------
+class Plan:
+    """A plan for one problem shape, with device output buffers."""
+
+    def __init__(self, problem, rescue_threshold=None, use_graph=True, plain=False, force_p=0,
+                 keep_checkpoints=False, tune_table=None):
+        opts = ph_plan_opts_default()
+        if rescue_threshold is not None:
+            opts.rescue_threshold = float(rescue_threshold)
+        opts.use_graph = int(bool(use_graph))
+        opts.plain = int(bool(plain))
+        opts.force_p = int(force_p)
+        opts.keep_checkpoints = int(bool(keep_checkpoints))
+        self._tune = tune_table.encode() if tune_table else None
+        opts.tune_table_path = self._tune
+        shape, self._keep = shape_of(problem)
+        self.handle = ph_plan_create(shape, opts)
+        self.num_pairs, self.num_cells, self.max_read_len, self.max_hap_len = ph_plan_info(self.handle)
+
+    def forward(self, dev: DeviceProblem, log10_params=None, out=None, status=None, stream=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(max(self.num_pairs, 1), dtype=torch.float64, device="cuda")
+        if status is None:
+            status = torch.empty(max(self.num_pairs, 1), dtype=torch.uint8, device="cuda")
+        lp = None if log10_params is None else ctypes.c_void_p(log10_params.data_ptr())
+        ph_forward_batch(self.handle, dev.c, lp, ctypes.c_void_p(out.data_ptr()),
+                         ctypes.c_void_p(status.data_ptr()), stream or current_stream())
+        return out[:self.num_pairs], status[:self.num_pairs]
+
+    def validate(self, dev: DeviceProblem, stream=None):
+        ph_validate(self.handle, dev.c, stream or current_stream())
+
+    def stage_ms(self):
+        return ph_plan_stage_ms(self.handle)
+
+    def rescued(self) -> int:
+        return ph_plan_rescued(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ph_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,558 @@
+// Host runtime and C ABI of libpairhmm (include/ph.h).
+//
+// A plan is built once per problem shape: it validates the batch structure
+// and lengths, assigns every read length to a kernel configuration (lanes P
+// per pair, rows K per lane; the paper's (p, k) template grid, Section
+// III-B/III-C), counts the pairs of every length bin, and allocates the
+// device scratch.  A forward call then enqueues, on the caller's stream:
+//   1. (explicit-parameter mode) exponentiation of the log10 parameters;
+//   2. on-device binning: histogram, scan and scatter of the pairs by
+//      (length bin, haplotype length), Section III-A stage 3 / Section III-C;
+//   3. one persistent FP32 sweep per non-empty bin, longest bin first, as
+//      parallel branches (Section III-C runs one kernel per index list on its
+//      own stream);
+//   4. the FP64 sweep over the pairs whose FP32 sum fell below the rescue
+//      threshold, one persistent launch per read-length class.
+// The whole sequence is captured once into a HIP graph and replayed while
+// the problem and output pointers stay the same.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <fstream>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/ph.h"
+#include "ph_internal.h"
+
+using namespace ph;
+
+namespace {
+
+thread_local std::string g_err;
+
+ph_status fail(ph_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(x)                                                                           \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess) return fail(PH_ERR_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+struct TuneEntry {
+    int max_m, P, K;
+};
+
+constexpr int kSideStreams = 4;
+constexpr int kStageEvents = 5;
+
+std::once_flag g_lut_once;
+hipError_t g_lut_status = hipSuccess;
+
+int rescue_class_of(int m) { return m < 128 ? 0 : m < 256 ? 1 : m < 512 ? 2 : 3; }
+
+std::vector<TuneEntry> default_table(int force_p)
+{
+    std::vector<TuneEntry> t;
+    if (force_p) {
+        for (int K = 1; K <= 16; ++K)
+            if (fwd32_supported(force_p, K) && force_p * K - 1 <= kMaxReadLen)
+                t.push_back({force_p * K - 1, force_p, K});
+        return t;
+    }
+    for (int K = 1; K <= 16; ++K) t.push_back({16 * K - 1, 16, K});
+    for (int K = 5; K <= 16; ++K) t.push_back({64 * K - 1, 64, K});
+    return t;
+}
+
+ph_status read_table(const char *path, std::vector<TuneEntry> &t)
+{
+    std::ifstream f(path);
+    if (!f) return fail(PH_ERR_INVALID, "cannot open tune table %s", path);
+    std::string line;
+    t.clear();
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream ss(line);
+        TuneEntry e;
+        if (!(ss >> e.max_m >> e.P >> e.K)) return fail(PH_ERR_INVALID, "bad tune line: %s", line.c_str());
+        if (!fwd32_supported(e.P, e.K)) return fail(PH_ERR_UNSUPPORTED, "tune entry P=%d K=%d not compiled", e.P, e.K);
+        if (e.max_m > e.P * e.K - 1 || e.max_m < 1)
+            return fail(PH_ERR_INVALID, "tune entry max_m=%d exceeds P*K-1 for P=%d K=%d", e.max_m, e.P, e.K);
+        t.push_back(e);
+    }
+    std::sort(t.begin(), t.end(), [](const TuneEntry &a, const TuneEntry &b) { return a.max_m < b.max_m; });
+    if (t.empty()) return fail(PH_ERR_INVALID, "empty tune table %s", path);
+    if ((int)t.size() > kMaxBins) return fail(PH_ERR_INVALID, "tune table has more than %d entries", kMaxBins);
+    return PH_OK;
+}
+
+}  // namespace
+
+struct ph_plan {
+    int device = 0;
+    int cus = 0;
+    ph_plan_opts opts{};
+    double threshold = 1e-28;
+    int32_t nb = 0, nr = 0, nh = 0;
+    int64_t P = 0, cells = 0, nread_bases = 0, nhap_bases = 0;
+    int32_t max_m = 0, max_n = 0;
+
+    std::vector<TuneEntry> table;      // bin b = table[table.size()-1-b] (longest first)
+    std::vector<int64_t> bin_pairs;    // pairs per bin (host count)
+    std::vector<int> bin_grid;         // persistent grid per bin (0 = empty)
+    int64_t class_pairs[kRescueClasses] = {0, 0, 0, 0};
+    int rescue_grid[kRescueClasses] = {0, 0, 0, 0};
+    int plain_K = 0, plain_grid = 0;
+
+    int64_t *d_out_offset = nullptr;
+    int16_t *d_m2bin = nullptr;
+    int32_t *d_bin_G = nullptr;
+    int32_t *d_hist = nullptr;
+    PairRec *d_recs = nullptr;
+    Book *d_book = nullptr;
+    int32_t *d_rescue = nullptr;
+    double *d_lin = nullptr;
+    int64_t lin_cap = 0;
+
+    hipStream_t cap = nullptr;
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork = nullptr, join[kSideStreams] = {};
+    hipEvent_t ev[kStageEvents] = {};
+    bool stages_recorded = false;
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void *> graph_key;
+
+    hipStream_t last_stream = nullptr;
+    bool forward_done = false;
+};
+
+namespace {
+
+void free_plan(ph_plan *p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    void *bufs[] = {p->d_out_offset, p->d_m2bin, p->d_bin_G, p->d_hist, p->d_recs, p->d_book, p->d_rescue, p->d_lin};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    for (auto &e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : p->join)
+        if (e) (void)hipEventDestroy(e);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    for (auto &s : p->side)
+        if (s) (void)hipStreamDestroy(s);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    delete p;
+}
+
+template <typename T>
+ph_status dalloc(T **ptr, size_t count)
+{
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc((void **)ptr, bytes);
+    if (e != hipSuccess) return fail(PH_ERR_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    return PH_OK;
+}
+
+ph_status check_problem(const ph_plan *p, const ph_problem *pb)
+{
+    if (!pb) return fail(PH_ERR_INVALID, "problem is NULL");
+    if (pb->num_batches != p->nb || pb->num_reads != p->nr || pb->num_haps != p->nh)
+        return fail(PH_ERR_PLAN_MISMATCH, "problem has %d batches, %d reads, %d haplotypes; plan has %d, %d, %d",
+                    pb->num_batches, pb->num_reads, pb->num_haps, p->nb, p->nr, p->nh);
+    if (p->P == 0) return PH_OK;
+    if (!pb->batch_read_begin || !pb->batch_hap_begin || !pb->read_offset || !pb->hap_offset ||
+        !pb->read_bases || !pb->hap_bases)
+        return fail(PH_ERR_INVALID, "problem has a NULL array");
+    return PH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ph_plan_opts_default(ph_plan_opts *o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->rescue_threshold = 1e-28;
+    o->use_graph = 1;
+}
+
+const char *ph_last_error(void) { return g_err.c_str(); }
+
+const char *ph_version(void) { return "libpairhmm 0.1 gfx950"; }
+
+ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_plan **out)
+{
+    g_err.clear();
+    if (!shape || !out) return fail(PH_ERR_INVALID, "shape or out is NULL");
+    *out = nullptr;
+    ph_plan_opts opts;
+    if (opts_in) opts = *opts_in; else ph_plan_opts_default(&opts);
+    const int32_t nb = shape->num_batches, nr = shape->num_reads, nh = shape->num_haps;
+    if (nb < 0 || nr < 0 || nh < 0) return fail(PH_ERR_INVALID, "negative counts");
+    if (nb > 0 && (!shape->batch_read_begin || !shape->batch_hap_begin))
+        return fail(PH_ERR_INVALID, "batch arrays are NULL");
+    if (!shape->read_offset || !shape->hap_offset) return fail(PH_ERR_INVALID, "offset arrays are NULL");
+    if (opts.force_p && opts.force_p != 16 && opts.force_p != 32 && opts.force_p != 64)
+        return fail(PH_ERR_INVALID, "force_p must be 0, 16, 32 or 64");
+
+    // --- shape validation ---------------------------------------------------
+    const int32_t *rb = shape->batch_read_begin, *hb = shape->batch_hap_begin;
+    const int64_t *ro = shape->read_offset, *ho = shape->hap_offset;
+    if (ro[0] != 0 || ho[0] != 0) return fail(PH_ERR_INVALID, "read_offset[0] and hap_offset[0] must be 0");
+    int32_t max_m = 0, max_n = 0;
+    for (int32_t r = 0; r < nr; ++r) {
+        int64_t m = ro[r + 1] - ro[r];
+        if (m < 1) return fail(PH_ERR_INVALID, "read %d has length %lld", r, (long long)m);
+        if (m > kMaxReadLen) return fail(PH_ERR_UNSUPPORTED, "read %d has length %lld > %d", r, (long long)m, kMaxReadLen);
+        max_m = std::max<int32_t>(max_m, (int32_t)m);
+    }
+    for (int32_t h = 0; h < nh; ++h) {
+        int64_t n = ho[h + 1] - ho[h];
+        if (n < 1) return fail(PH_ERR_INVALID, "haplotype %d has length %lld", h, (long long)n);
+        if (n > (1 << 30)) return fail(PH_ERR_UNSUPPORTED, "haplotype %d is too long", h);
+        max_n = std::max<int32_t>(max_n, (int32_t)n);
+    }
+    if (nb > 0 && (rb[0] != 0 || hb[0] != 0)) return fail(PH_ERR_INVALID, "batch ranges must start at 0");
+    std::vector<int64_t> out_off(nb + 1, 0);
+    for (int32_t q = 0; q < nb; ++q) {
+        if (rb[q + 1] < rb[q] || hb[q + 1] < hb[q] || rb[q + 1] > nr || hb[q + 1] > nh)
+            return fail(PH_ERR_INVALID, "batch %d has a bad read or haplotype range", q);
+        out_off[q + 1] = out_off[q] + (int64_t)(rb[q + 1] - rb[q]) * (hb[q + 1] - hb[q]);
+    }
+    const int64_t P = nb ? out_off[nb] : 0;
+    if (P >= (int64_t)1 << 31) return fail(PH_ERR_UNSUPPORTED, "%lld pairs exceed 2^31 - 1", (long long)P);
+
+    std::unique_ptr<ph_plan, void (*)(ph_plan *)> p(new ph_plan, free_plan);
+    p->opts = opts;
+    p->threshold = opts.rescue_threshold > 0 ? opts.rescue_threshold : 1e-28;
+    p->nb = nb; p->nr = nr; p->nh = nh; p->P = P;
+    p->nread_bases = ro[nr];
+    p->nhap_bases = ho[nh];
+    p->max_m = max_m;
+    p->max_n = max_n;
+    HIPCHK(hipGetDevice(&p->device));
+    HIPCHK(hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device));
+    std::call_once(g_lut_once, [] { g_lut_status = upload_luts(); });
+    HIPCHK(g_lut_status);
+
+    // --- length bins ----------------------------------------------------------
+    if (opts.tune_table_path) {
+        ph_status st = read_table(opts.tune_table_path, p->table);
+        if (st != PH_OK) return st;
+    } else {
+        p->table = default_table(opts.force_p);
+    }
+    const int nbins = (int)p->table.size();
+    if (max_m > p->table.back().max_m)
+        return fail(PH_ERR_UNSUPPORTED, "read length %d exceeds the longest configured bin (%d)", max_m,
+                    p->table.back().max_m);
+    std::vector<int16_t> m2bin(kMaxReadLen + 2, 0);
+    for (int m = 1; m <= kMaxReadLen + 1; ++m) {
+        int e = 0;
+        while (e < nbins - 1 && p->table[e].max_m < m) ++e;
+        m2bin[m] = (int16_t)(nbins - 1 - e);
+    }
+    std::vector<int32_t> binG(nbins);
+    for (int b = 0; b < nbins; ++b) binG[b] = 64 / p->table[nbins - 1 - b].P;
+    p->bin_pairs.assign(nbins, 0);
+    int64_t cells = 0;
+    for (int32_t q = 0; q < nb; ++q) {
+        const int64_t H = hb[q + 1] - hb[q];
+        int64_t nsum = 0;
+        for (int32_t h = hb[q]; h < hb[q + 1]; ++h) nsum += ho[h + 1] - ho[h];
+        for (int32_t r = rb[q]; r < rb[q + 1]; ++r) {
+            const int m = (int)(ro[r + 1] - ro[r]);
+            p->bin_pairs[m2bin[m]] += H;
+            p->class_pairs[rescue_class_of(m)] += H;
+            cells += (int64_t)m * nsum;
+        }
+    }
+    p->cells = cells;
+    p->bin_grid.assign(nbins, 0);
+    for (int b = 0; b < nbins; ++b) {
+        if (!p->bin_pairs[b]) continue;
+        const TuneEntry &e = p->table[nbins - 1 - b];
+        const int64_t tiles = (p->bin_pairs[b] + binG[b] - 1) / binG[b];
+        const int64_t cap = (int64_t)p->cus * fwd32_blocks_per_cu(e.P, e.K);
+        p->bin_grid[b] = (int)std::min<int64_t>(tiles, cap);
+    }
+    for (int c = 0; c < kRescueClasses; ++c)
+        if (p->class_pairs[c])
+            p->rescue_grid[c] = (int)std::min<int64_t>(p->class_pairs[c], (int64_t)p->cus * fwd64_blocks_per_cu(c));
+    p->plain_K = (max_m + 1 + 63) / 64;
+    if (p->plain_K < 1) p->plain_K = 1;
+    p->plain_grid = (int)std::min<int64_t>(std::max<int64_t>(P, 1), (int64_t)p->cus * plain32_blocks_per_cu(p->plain_K));
+
+    // --- device scratch -------------------------------------------------------
+    ph_status st;
+    if ((st = dalloc(&p->d_out_offset, nb + 1))) return st;
+    if ((st = dalloc(&p->d_m2bin, m2bin.size()))) return st;
+    if ((st = dalloc(&p->d_bin_G, kMaxBins))) return st;
+    if ((st = dalloc(&p->d_hist, kMaxKeys))) return st;
+    if ((st = dalloc(&p->d_recs, std::max<int64_t>(P, 1)))) return st;
+    if ((st = dalloc(&p->d_book, 1))) return st;
+    if ((st = dalloc(&p->d_rescue, (size_t)kRescueClasses * std::max<int64_t>(P, 1)))) return st;
+    HIPCHK(hipMemcpy(p->d_out_offset, out_off.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(p->d_m2bin, m2bin.data(), m2bin.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(p->d_bin_G, binG.data(), nbins * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(p->d_book, 0, sizeof(Book)));
+
+    HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+    for (auto &s : p->side) HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
+    for (auto &e : p->join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto &e : p->ev) HIPCHK(hipEventCreate(&e));
+    *out = p.release();
+    return PH_OK;
+}
+
+ph_status ph_plan_info(const ph_plan *p, int64_t *num_pairs, int64_t *num_cells, int32_t *max_read_len,
+                       int32_t *max_hap_len)
+{
+    if (!p) return fail(PH_ERR_INVALID, "plan is NULL");
+    if (num_pairs) *num_pairs = p->P;
+    if (num_cells) *num_cells = p->cells;
+    if (max_read_len) *max_read_len = p->max_m;
+    if (max_hap_len) *max_hap_len = p->max_n;
+    return PH_OK;
+}
+
+void ph_plan_destroy(ph_plan *p) { free_plan(p); }
+
+}  // extern "C"
+
+namespace {
+
+BinArgs bin_args(ph_plan *p, const ph_problem *pb)
+{
+    BinArgs a{};
+    a.num_pairs = p->P;
+    a.num_batches = p->nb;
+    a.out_offset = p->d_out_offset;
+    a.batch_read_begin = pb->batch_read_begin;
+    a.batch_hap_begin = pb->batch_hap_begin;
+    a.read_offset = pb->read_offset;
+    a.hap_offset = pb->hap_offset;
+    a.m2bin = p->d_m2bin;
+    a.num_bins = (int32_t)p->table.size();
+    a.bin_G = p->d_bin_G;
+    a.hist = p->d_hist;
+    a.recs = p->d_recs;
+    a.book = p->d_book;
+    return a;
+}
+
+SweepArgs sweep_args(ph_plan *p, const ph_problem *pb, const double *lin, double *out, uint8_t *status)
+{
+    SweepArgs a{};
+    a.pb.read_offset = pb->read_offset;
+    a.pb.read_bases = pb->read_bases;
+    a.pb.bq = pb->base_qual;
+    a.pb.iq = pb->ins_qual;
+    a.pb.dq = pb->del_qual;
+    a.pb.gq = pb->gcp_qual;
+    a.pb.hap_offset = pb->hap_offset;
+    a.pb.hap_bases = pb->hap_bases;
+    a.pb.log10_params = nullptr;
+    a.lin_params = lin;
+    a.recs = p->d_recs;
+    a.book = p->d_book;
+    a.out_log10 = out;
+    a.out_status = status;
+    a.rescue_list = p->d_rescue;
+    a.rescue_stride = std::max<int64_t>(p->P, 1);
+    a.threshold = p->threshold;
+    a.floor64 = std::ldexp(1.0, -1000);
+    a.num_bins = (int32_t)p->table.size();
+    for (int b = 0; b < a.num_bins; ++b) {
+        const TuneEntry &e = p->table[a.num_bins - 1 - b];
+        a.bins[b] = {e.P, e.K};
+    }
+    a.plain_count = (int32_t)p->P;
+    return a;
+}
+
+// Enqueue the whole forward sequence on stream s.
+ph_status enqueue_forward(ph_plan *p, const ph_problem *pb, const float *log10_params, double *out,
+                          uint8_t *status, hipStream_t s)
+{
+    const double *lin = nullptr;
+    HIPCHK(hipEventRecord(p->ev[0], s));
+    if (log10_params) {
+        HIPCHK(launch_prep_params(log10_params, p->nread_bases, p->d_lin, s));
+        lin = p->d_lin;
+    }
+    const BinArgs ba = bin_args(p, pb);
+    const int nkeys = ba.num_bins * kBuckets;
+    HIPCHK(launch_reset_keys(p->d_hist, nkeys, p->d_book, s));
+    if (p->opts.plain) {
+        HIPCHK(launch_plain_records(ba, s));
+    } else {
+        HIPCHK(launch_bin_count(ba, s));
+        HIPCHK(launch_bin_scan(ba, s));
+        HIPCHK(launch_bin_scatter(ba, s));
+    }
+    HIPCHK(hipEventRecord(p->ev[1], s));
+    const SweepArgs sa = sweep_args(p, pb, lin, out, status);
+    if (p->opts.plain) {
+        HIPCHK(launch_plain32(sa, p->plain_K, p->plain_grid, s));
+    } else {
+        // bins longest first, round-robin over side streams forked from s
+        HIPCHK(hipEventRecord(p->fork, s));
+        bool used[kSideStreams] = {};
+        int next = 0;
+        for (int b = 0; b < sa.num_bins; ++b) {
+            if (!p->bin_grid[b]) continue;
+            const int k = next++ % kSideStreams;
+            if (!used[k]) {
+                HIPCHK(hipStreamWaitEvent(p->side[k], p->fork, 0));
+                used[k] = true;
+            }
+            HIPCHK(launch_fwd32(sa, sa.bins[b].P, sa.bins[b].K, b, p->bin_grid[b], p->side[k]));
+        }
+        for (int k = 0; k < kSideStreams; ++k) {
+            if (!used[k]) continue;
+            HIPCHK(hipEventRecord(p->join[k], p->side[k]));
+            HIPCHK(hipStreamWaitEvent(s, p->join[k], 0));
+        }
+    }
+    HIPCHK(hipEventRecord(p->ev[2], s));
+    if (!p->opts.plain) {
+        for (int c = 0; c < kRescueClasses; ++c)
+            if (p->rescue_grid[c]) HIPCHK(launch_fwd64(sa, c, p->rescue_grid[c], s));
+    }
+    HIPCHK(hipEventRecord(p->ev[3], s));
+    return PH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ph_status ph_forward_batch(ph_plan *p, const ph_problem *pb, const float *log10_params, double *out_log10L,
+                           uint8_t *out_status, void *stream_v)
+{
+    g_err.clear();
+    if (!p) return fail(PH_ERR_INVALID, "plan is NULL");
+    ph_status st = check_problem(p, pb);
+    if (st != PH_OK) return st;
+    if (p->P == 0) return PH_OK;
+    if (!out_log10L) return fail(PH_ERR_INVALID, "out_log10L is NULL");
+    if (!log10_params && (!pb->base_qual || !pb->ins_qual || !pb->del_qual || !pb->gcp_qual))
+        return fail(PH_ERR_INVALID, "Phred arrays are NULL and no log10 parameters were given");
+    hipStream_t s = (hipStream_t)stream_v;
+    if (log10_params && p->lin_cap < p->nread_bases) {
+        if (p->d_lin) HIPCHK(hipFree(p->d_lin));
+        p->d_lin = nullptr;
+        if ((st = dalloc(&p->d_lin, (size_t)p->nread_bases * 8))) return st;
+        p->lin_cap = p->nread_bases;
+        if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+        if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+        p->graph_key.clear();
+    }
+
+    if (p->opts.use_graph) {
+        std::vector<const void *> key = {pb->batch_read_begin, pb->batch_hap_begin, pb->read_offset,
+                                         pb->read_bases, pb->base_qual, pb->ins_qual, pb->del_qual,
+                                         pb->gcp_qual, pb->hap_offset, pb->hap_bases, log10_params,
+                                         out_log10L, out_status};
+        if (!p->exec || key != p->graph_key) {
+            if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+            if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+            HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
+            st = enqueue_forward(p, pb, log10_params, out_log10L, out_status, p->cap);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(p->cap, &g);
+            if (st != PH_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+            if (e != hipSuccess) return fail(PH_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            p->graph = g;
+            HIPCHK(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0));
+            p->graph_key = key;
+        }
+        HIPCHK(hipGraphLaunch(p->exec, s));
+    } else {
+        st = enqueue_forward(p, pb, log10_params, out_log10L, out_status, s);
+        if (st != PH_OK) return st;
+    }
+    p->last_stream = s;
+    p->stages_recorded = true;
+    p->forward_done = true;
+    return PH_OK;
+}
+
+ph_status ph_backward_batch(ph_plan *p, const ph_problem *pb, const float *log10_params,
+                            const double *grad_log10L, float *grad_params, void *stream)
+{
+    (void)pb; (void)log10_params; (void)grad_log10L; (void)grad_params; (void)stream;
+    g_err.clear();
+    if (!p) return fail(PH_ERR_INVALID, "plan is NULL");
+    return fail(PH_ERR_UNSUPPORTED, "adjoint sweep not available in this build");
+}
+
+ph_status ph_validate(ph_plan *p, const ph_problem *pb, void *stream_v)
+{
+    g_err.clear();
+    if (!p) return fail(PH_ERR_INVALID, "plan is NULL");
+    ph_status st = check_problem(p, pb);
+    if (st != PH_OK) return st;
+    hipStream_t s = (hipStream_t)stream_v;
+    DevProblem d{};
+    d.read_bases = pb->read_bases;
+    d.hap_bases = pb->hap_bases;
+    HIPCHK(launch_reset_keys(p->d_hist, 0, p->d_book, s));
+    HIPCHK(launch_validate(d, p->nread_bases, p->nhap_bases, p->d_book, s));
+    int32_t bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, &p->d_book->bad_code, sizeof(bad), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) return fail(PH_ERR_INVALID, "%d base codes outside 0..4", bad);
+    return PH_OK;
+}
+
+ph_status ph_plan_stage_ms(ph_plan *p, float ms[4])
+{
+    if (!p || !ms) return fail(PH_ERR_INVALID, "NULL argument");
+    if (!p->stages_recorded) return fail(PH_ERR_STATE, "no forward call recorded");
+    HIPCHK(hipEventSynchronize(p->ev[3]));
+    HIPCHK(hipEventElapsedTime(&ms[0], p->ev[0], p->ev[1]));
+    HIPCHK(hipEventElapsedTime(&ms[1], p->ev[1], p->ev[2]));
+    HIPCHK(hipEventElapsedTime(&ms[2], p->ev[2], p->ev[3]));
+    ms[3] = 0.0f;
+    return PH_OK;
+}
+
+ph_status ph_plan_rescued(ph_plan *p, int64_t *count)
+{
+    if (!p || !count) return fail(PH_ERR_INVALID, "NULL argument");
+    if (!p->forward_done) return fail(PH_ERR_STATE, "no forward call recorded");
+    HIPCHK(hipEventSynchronize(p->ev[3]));
+    int32_t c[kRescueClasses];
+    HIPCHK(hipMemcpy(c, p->d_book->rescue_count, sizeof(c), hipMemcpyDeviceToHost));
+    *count = 0;
+    for (int i = 0; i < kRescueClasses; ++i) *count += c[i];
+    return PH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libpairhmm.  Not part of the public ABI (that is include/ph.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ph {
+
+// Haplotype codes: A C G T N, plus PAD for columns past the end of a
+// haplotype.  PAD has emission 0 in every row, so a PAD column adds exactly
+// zero to the row-m sum.
+constexpr int kCodes = 6;
+constexpr int kPad = 5;
+
+// Haplotype ring buffer per lane group in LDS: 4 chunks of 64 columns plus a
+// 64-byte mirror of chunk 0, so a block of 64 consecutive steps never wraps.
+constexpr int kChunk = 64;
+constexpr int kRing = 256;
+constexpr int kRingAlloc = 320;
+
+constexpr int kMaxBins = 32;
+constexpr int kBuckets = 128;            // haplotype-length buckets per bin
+constexpr int kMaxKeys = kMaxBins * kBuckets;
+constexpr int kMaxReadLen = 1023;        // 64 lanes x 16 rows minus the absorbing row
+constexpr int kRescueClasses = 4;        // FP64 sweep: 64 lanes x {2, 4, 8, 16} rows
+
+// One read/haplotype pair: indices into the problem and into the output.
+struct PairRec {
+    int32_t read, hap, out, n;
+};
+
+struct DevProblem {
+    const int64_t *read_offset;
+    const uint8_t *read_bases, *bq, *iq, *dq, *gq;
+    const int64_t *hap_offset;
+    const uint8_t *hap_bases;
+    const float *log10_params;  // NULL: derive from Phred
+};
+
+struct BinCfg {
+    int32_t P, K;        // lanes per pair, rows per lane
+};
+
+// Device-side bookkeeping written by the binning kernels and read by the
+// sweeps; lives in one plan-owned buffer.
+struct Book {
+    int32_t bin_rec_begin[kMaxBins + 1];   // record range of every bin
+    int32_t bin_tile_begin[kMaxBins + 1];  // tile range of every bin (persistent sweep)
+    int32_t tile_counter;                  // plain sweep work cursor
+    int32_t bin_counter[kMaxBins];         // FP32 sweep work cursor of every bin
+    int32_t rescue_count[kRescueClasses];  // FP64 queue lengths
+    int32_t rescue_counter[kRescueClasses];// FP64 sweep work cursors
+    int32_t bad_code;                      // validation: count of codes > 4
+};
+
+struct BinArgs {
+    int64_t num_pairs;
+    int32_t num_batches;
+    const int64_t *out_offset;   // [num_batches+1]
+    const int32_t *batch_read_begin, *batch_hap_begin;
+    const int64_t *read_offset, *hap_offset;
+    const int16_t *m2bin;        // [kMaxReadLen+2]
+    int32_t num_bins;
+    const int32_t *bin_G;        // pairs per tile of each bin
+    int32_t *hist;               // [kMaxKeys]
+    PairRec *recs;               // [num_pairs]
+    Book *book;
+};
+
+struct SweepArgs {
+    DevProblem pb;
+    const double *lin_params;    // explicit mode: [sum m][8] linear parameters, else NULL
+    const PairRec *recs;
+    Book *book;
+    double *out_log10;
+    uint8_t *out_status;
+    int32_t *rescue_list;        // [kRescueClasses][num_pairs]
+    int64_t rescue_stride;       // = num_pairs
+    double threshold;            // FP32: scaled-sum rescue threshold
+    double floor64;              // FP64: scaled-sum floor
+    int32_t num_bins;
+    BinCfg bins[kMaxBins];
+    int32_t mode;                // 0 binned FP32 + rescue, 1 plain FP32, 2 FP64 rescue
+    int32_t rescue_class;        // FP64: which queue
+    int32_t plain_count;         // plain: number of records (tiles of 1 pair)
+};
+
+// Launchers (ph_kernels.hip).  All enqueue on `s` and return the HIP status.
+hipError_t upload_luts();
+hipError_t launch_bin_count(const BinArgs &a, hipStream_t s);
+hipError_t launch_bin_scan(const BinArgs &a, hipStream_t s);
+hipError_t launch_bin_scatter(const BinArgs &a, hipStream_t s);
+hipError_t launch_plain_records(const BinArgs &a, hipStream_t s);
+hipError_t launch_fwd32(const SweepArgs &a, int P, int K, int bin, int grid, hipStream_t s);
+hipError_t launch_plain32(const SweepArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_fwd64(const SweepArgs &a, int cls, int grid, hipStream_t s);
+hipError_t launch_prep_params(const float *lg, int64_t npos, double *lin, hipStream_t s);
+hipError_t launch_validate(const DevProblem &pb, int64_t nread_bases, int64_t nhap_bases,
+                           Book *book, hipStream_t s);
+hipError_t launch_reset_keys(int32_t *hist, int nkeys, Book *book, hipStream_t s);
+int fwd32_blocks_per_cu(int P, int K);
+int fwd64_blocks_per_cu(int cls);
+int plain32_blocks_per_cu(int K);
+bool fwd32_supported(int P, int K);
+
+}  // namespace ph

@@ -1,0 +1,729 @@
+// HIP kernels of libpairhmm for gfx950 (CDNA4, wave64).
+//
+// The Pair-HMM forward recurrences (arXiv 2411.11547, Section II-A, Eq. 1-4)
+// are swept along anti-diagonals inside one wavefront, after the paper's
+// wavefront design (Section III-B): a group of P lanes computes one
+// read/haplotype pair; lane t owns the K consecutive read rows
+// tK+1 .. tK+K and keeps their M, I and D values in registers; at step s it
+// updates column j = s - t + 1 of its rows and hands the values of its last
+// row to lane t+1 with a DPP lane shift (the paper uses warp shuffles).  The
+// haplotype is streamed through the lanes: every lane reads its column's
+// code from a per-group ring buffer in LDS.  Emissions come from a
+// per-lane table E[code][row] in LDS (Section III-B's E array), so a cell
+// costs one LDS value and seven VALU operations:
+//
+//   X  = beta_i I(i-1,j-1) + Dt(i-1,j-1) ;  X = alpha_i M(i-1,j-1) + X
+//   M(i,j) = lam_ij X
+//   I(i,j) = delta_i M(i-1,j) + eps_i I(i-1,j)
+//   Dt(i,j) = (beta_{i+1} zeta_i) M(i,j-1) + eps_i Dt(i,j-1)
+//
+// where Dt(i,j) = beta_{i+1} D(i,j) is D pre-multiplied by the next row's
+// beta, which folds Eq. (1)'s beta_i (I + D) into one FMA.
+//
+// Differences from the paper's kernel:
+//  * Rows past the read end are "absorbing": row m+1 has lam = 0,
+//    delta = eps = 1, so I(m+1,j) = M(m,j) + I(m,j), and later rows pass I
+//    down unchanged (delta = 0, eps = 1).  The last register of the group's
+//    last lane therefore always holds the quantity Section II-A sums into L,
+//    whatever m is, and no per-lane select is needed.  (The paper pads reads
+//    with N, which would change L if read at row pK.)
+//  * Columns past the haplotype end carry a PAD code whose emission is 0, so
+//    groups of one wave may have different n and still add only exact zeros.
+//  * D(0, j) = 1/n is scaled by 2^120 (FP32) or 2^1020 (FP64) so that the
+//    sweep stays inside the normal range; pairs whose scaled FP32 sum falls
+//    below a threshold are queued and recomputed by the FP64 sweep.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ph_internal.h"
+
+namespace ph {
+
+__constant__ double c_prob[256];  // Phred q -> 10^(-q/10), computed on the host in FP64
+
+hipError_t upload_luts()
+{
+    double t[256];
+    for (int q = 0; q < 256; ++q) t[q] = pow(10.0, -(double)q / 10.0);
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_prob), t, sizeof(t));
+}
+
+// ---------------------------------------------------------------------------
+// lane shifts inside groups of P lanes: lane t receives lane t-1's value,
+// the first lane of each group receives 0.
+// ---------------------------------------------------------------------------
+template <int P>
+__device__ __forceinline__ uint32_t shift_up_zero(uint32_t v)
+{
+    int x = (int)v;
+    if constexpr (P == 16) {
+        x = __builtin_amdgcn_mov_dpp(x, 0x111 /* row_shr:1 */, 0xf, 0xf, true);
+    } else if constexpr (P == 64) {
+        x = __builtin_amdgcn_mov_dpp(x, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
+    } else {
+        static_assert(P == 32, "lane groups of 16, 32 or 64");
+        // lanes 16 and 48 take lane 15 / 47 from the previous 16-lane row,
+        // the rest shift inside their row; lanes 0 and 32 keep 0.
+        int t = __builtin_amdgcn_update_dpp(0, x, 0x142 /* row_bcast:15 */, 0xa, 0x1, false);
+        x = __builtin_amdgcn_update_dpp(t, x, 0x111 /* row_shr:1 */, 0xf, 0xf, false);
+    }
+    return (uint32_t)x;
+}
+
+template <int P>
+__device__ __forceinline__ float shift_up(float v)
+{
+    return __builtin_bit_cast(float, shift_up_zero<P>(__builtin_bit_cast(uint32_t, v)));
+}
+
+template <int P>
+__device__ __forceinline__ double shift_up(double v)
+{
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    uint32_t lo = shift_up_zero<P>((uint32_t)u);
+    uint32_t hi = shift_up_zero<P>((uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <typename T>
+struct Range;
+template <>
+struct Range<float> {
+    static constexpr int kExp = 120;
+};
+template <>
+struct Range<double> {
+    static constexpr int kExp = 1020;
+};
+
+// Per-lane LDS layout for one configuration: E[code][plane][lane] of 8-byte
+// entries (two FP32 rows or one FP64 row per plane), then the haplotype
+// rings of the groups.  Entry (c, q, lane) sits at
+// c*CODE_BYTES + q*512 + lane*8, so 64 lanes read 512 consecutive bytes when
+// they look up the same code and never conflict when they look up different
+// codes.
+template <typename T, int P, int K>
+struct Cfg {
+    static constexpr int G = 64 / P;
+    static constexpr int RPP = 8 / (int)sizeof(T);  // rows per plane entry
+    static constexpr int NPL = (K + RPP - 1) / RPP;
+    static constexpr int KP = NPL * RPP;
+    static constexpr int CODE_BYTES = NPL * 512;
+    static constexpr int E_BYTES = kCodes * CODE_BYTES;
+    static constexpr int LDS_BYTES = E_BYTES + G * kRingAlloc;
+};
+
+// Parameters of one read row in linear space.  Phred mode decodes the
+// quality bytes through the FP64 table; explicit mode reads the row's
+// exponentiated parameters, written once per call by k_prep_params.
+struct RowPar {
+    double a, b, d, e, z, lm, lx;
+};
+
+__device__ __forceinline__ RowPar load_row(const DevProblem &pb, const double *lin, int64_t pos)
+{
+    RowPar r;
+    if (lin) {
+        const double *p = lin + pos * 8;
+        r.a = p[0];
+        r.b = p[1];
+        r.d = p[2];
+        r.e = p[3];
+        r.z = p[4];
+        r.lm = p[5];
+        r.lx = p[6];
+    } else {
+        const double Q = c_prob[pb.bq[pos]];
+        r.d = c_prob[pb.iq[pos]];
+        r.z = c_prob[pb.dq[pos]];
+        r.e = c_prob[pb.gq[pos]];
+        r.a = 1.0 - r.d - r.z;
+        r.b = 1.0 - r.e;
+        r.lm = 1.0 - Q;
+        r.lx = Q / 3.0;
+    }
+    return r;
+}
+
+__device__ __forceinline__ double load_beta(const DevProblem &pb, const double *lin, int64_t pos)
+{
+    if (lin) return lin[pos * 8 + 1];
+    return 1.0 - c_prob[pb.gq[pos]];
+}
+
+__device__ __forceinline__ uint32_t clamp_code(uint32_t c) { return c > 4u ? 4u : c; }
+
+template <typename T, int P, int K>
+__device__ __forceinline__ void load_lam(T *lam, const char *ebase)
+{
+    using C = Cfg<T, P, K>;
+#pragma unroll
+    for (int q = 0; q < C::NPL; ++q) {
+        if constexpr (sizeof(T) == 4) {
+            float2 v = *(const float2 *)(ebase + q * 512);
+            lam[2 * q] = v.x;
+            lam[2 * q + 1] = v.y;
+        } else {
+            lam[q] = *(const double *)(ebase + q * 512);
+        }
+    }
+}
+
+// Write chunk `chunk` (64 columns) of the group's haplotype into its ring.
+template <int P>
+__device__ __forceinline__ void ring_fill(uint8_t *ring, int chunk, const uint8_t *hap, int n, int t)
+{
+    constexpr int PER = kChunk / P;  // columns per lane
+    const int slot = chunk & 3;
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+        int x = t * PER + b;
+        int col = chunk * kChunk + x;
+        uint8_t c = col < n ? (uint8_t)clamp_code(hap[col]) : (uint8_t)kPad;
+        ring[slot * kChunk + x] = c;
+        if (slot == 0) ring[kRing + x] = c;
+    }
+}
+
+enum { kModeBinned = 0, kModePlain = 1, kModeRescue = 2 };
+
+// Next work item of a persistent wave: lane 0 bumps the cursor and the value
+// is read back from lane 0's register with v_readlane, which does not depend
+// on which lanes are active.
+__device__ __forceinline__ int next_tile(int32_t *cursor)
+{
+    int t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(cursor, 1);
+    return __builtin_amdgcn_readlane(t, 0);
+}
+
+// One anti-diagonal step of a lane: column j = s - t + 1 of rows tK+1..tK+K.
+// M, I, D hold column j-1 on entry and column j on exit; (Md, Id, Dd) are the
+// values of the row above the lane's first row at column j-1.
+template <typename T, int P, int K>
+__device__ __forceinline__ void cell_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md, T &Id, T &Dd,
+                                          const T *lam, const T (&al)[K], const T (&be)[K],
+                                          const T (&de)[K], const T (&ep)[K], const T (&zt)[K],
+                                          T edge, double &acc)
+{
+    const T Mu = shift_up<P>(M[K - 1]);
+    const T Iu = shift_up<P>(I[K - 1]);
+    const T Du = shift_up<P>(D[K - 1]) + edge;
+    T mup = Mu, iup = Iu, mdg = Md, idg = Id, ddg = Dd;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const T mo = M[r], io = I[r], dol = D[r];
+        T x = fma(be[r], idg, ddg);
+        x = fma(al[r], mdg, x);
+        const T mn = lam[r] * x;
+        const T in = fma(ep[r], iup, de[r] * mup);
+        const T dn = fma(ep[r], dol, zt[r] * mo);
+        M[r] = mn;
+        I[r] = in;
+        D[r] = dn;
+        mdg = mo;
+        idg = io;
+        ddg = dol;
+        mup = mn;
+        iup = in;
+    }
+    Md = Mu;
+    Id = Iu;
+    Dd = Du;
+    acc += (double)I[K - 1];
+}
+
+// Sweep one tile: up to G = 64/P pairs, one per lane group.  Group g takes
+// record rec_first + g (or rec_idx_list[rec_first + g]) if g < nvalid.
+template <typename T, int P, int K>
+__device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int rec_first,
+                           int nvalid, char *lds)
+{
+    using C = Cfg<T, P, K>;
+    const int lane = threadIdx.x;
+    const int g = lane / P;
+    const int t = lane % P;
+    const bool gvalid = g < nvalid;
+    const int ridx = gvalid ? (rec_idx_list ? rec_idx_list[rec_first + g] : rec_first + g) : 0;
+
+    PairRec rec = {0, 0, 0, 0};
+    if (gvalid) rec = A.recs[ridx];
+    const DevProblem &pb = A.pb;
+    const double *lin = A.lin_params;
+    const int64_t ro = gvalid ? pb.read_offset[rec.read] : 0;
+    const int m = gvalid ? (int)(pb.read_offset[rec.read + 1] - ro) : 0;
+    const int n = gvalid ? rec.n : 0;
+    const int64_t ho = gvalid ? pb.hap_offset[rec.hap] : 0;
+    const uint8_t *hap = pb.hap_bases + ho;
+
+    // the longest haplotype of the wave sets the number of steps
+    int nmax = n;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) nmax = max(nmax, __shfl_xor(nmax, off));
+    nmax = __builtin_amdgcn_readfirstlane(nmax);
+
+    // ---- prologue: parameters of my rows, my slice of the E table ----------
+    // Row parameters are computed one row at a time (a rolled loop keeps the
+    // FP64 decoding out of the sweep's register budget) and parked in the
+    // lane's own E-table entries, then loaded into registers; the E entries
+    // are written afterwards.  Loads use clamped row indices so that they
+    // stay inside the read; padding rows get their absorbing parameters.
+    char *E = lds;
+    char *mine = E + lane * 8;
+    uint8_t *ring = (uint8_t *)(lds + C::E_BYTES + g * kRingAlloc);
+    auto slot = [&](int c, int r) -> T * {
+        return (T *)(mine + c * C::CODE_BYTES + (r / C::RPP) * 512 + (r % C::RPP) * (int)sizeof(T));
+    };
+    const int mload = m > 0 ? m : 1;
+#pragma unroll 1
+    for (int r = 0; r < K; ++r) {
+        const int i = t * K + r;  // 0-based read row
+        const int ic = min(i, mload - 1);
+        const RowPar p = load_row(pb, lin, ro + ic);
+        const double bn = load_beta(pb, lin, ro + min(i + 1, mload - 1));
+        const bool real = i < m;
+        *slot(0, r) = real ? (T)p.a : (T)0;
+        *slot(1, r) = real ? (T)p.b : (T)0;
+        *slot(2, r) = real ? (T)p.d : (i == m ? (T)1 : (T)0);
+        *slot(3, r) = real ? (T)p.e : (T)1;
+        *slot(4, r) = (real && i + 1 < m) ? (T)(bn * p.z) : (T)0;
+    }
+    T al[K], be[K], de[K], ep[K], zt[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        al[r] = *slot(0, r);
+        be[r] = *slot(1, r);
+        de[r] = *slot(2, r);
+        ep[r] = *slot(3, r);
+        zt[r] = *slot(4, r);
+    }
+    // D(0, j) = 1/n scaled into range, pre-multiplied by beta_1; lane 0 only
+    T edge = 0;
+    if (t == 0 && m > 0) edge = (T)(ldexp(load_beta(pb, lin, ro), Range<T>::kExp) / (double)n);
+    // E[c][row] = lam of the row against haplotype code c (N matches all, PAD = 0)
+#pragma unroll 1
+    for (int r = 0; r < C::KP; ++r) {
+        const int i = t * K + r;
+        const int ic = min(i, mload - 1);
+        const RowPar p = load_row(pb, lin, ro + ic);
+        const bool real = (r < K) && (i < m);
+        const uint32_t code = clamp_code(pb.read_bases[ro + ic]);
+        const T lm = real ? (T)p.lm : (T)0, lx = real ? (T)p.lx : (T)0;
+#pragma unroll
+        for (int c = 0; c < kCodes; ++c) {
+            const bool match = code == (uint32_t)c || code == 4u || c == 4;
+            *slot(c, r) = c == kPad ? (T)0 : (match ? lm : lx);
+        }
+    }
+    // haplotype ring: PAD everywhere (negative columns read slot 3), then chunks 0 and 1
+    for (int x = t; x < kRingAlloc; x += P) ring[x] = (uint8_t)kPad;
+    __syncthreads();
+    ring_fill<P>(ring, 0, hap, n, t);
+    ring_fill<P>(ring, 1, hap, n, t);
+
+    // ---- sweep ----------------------------------------------------------------
+    T M[K], I[K], D[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) M[r] = I[r] = D[r] = 0;
+    T Md = 0, Id = 0, Dd = edge;  // row 0 at column 0
+    double acc = 0.0;
+    // steps run in pairs; a step past the last column only meets PAD columns
+    // in the last lane and adds exact zeros
+    const int total = (nmax + P - 1 + 1) & ~1;
+    const char *ebase_lane = E + lane * 8;
+
+    for (int s0 = 0; s0 < total; s0 += kChunk) {
+        ring_fill<P>(ring, s0 / kChunk + 2, hap, n, t);
+        __syncthreads();
+        const uint8_t *hp = ring + ((s0 - t) & (kRing - 1));
+        const int cnt = min(kChunk, total - s0);
+        T la[C::KP], lb[C::KP];
+        load_lam<T, P, K>(la, ebase_lane + (int)hp[0] * C::CODE_BYTES);
+        for (int u = 0; u < cnt; u += 2) {
+            load_lam<T, P, K>(lb, ebase_lane + (int)hp[u + 1] * C::CODE_BYTES);
+            cell_step<T, P, K>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, edge, acc);
+            load_lam<T, P, K>(la, ebase_lane + (int)hp[u + 2] * C::CODE_BYTES);
+            cell_step<T, P, K>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, edge, acc);
+        }
+        __syncthreads();
+    }
+
+    // ---- epilogue: the group's last lane owns the row-m sum ------------------
+    if (gvalid && t == P - 1) {
+        const double lg = log10(acc) - (double)Range<T>::kExp * 0.30102999566398119521;
+        A.out_log10[rec.out] = lg;
+        if (A.mode == kModeRescue) {
+            if (A.out_status) A.out_status[rec.out] = (acc >= A.floor64) ? 1 : 2;
+        } else {
+            const bool ok = (acc >= A.threshold) && (acc <= 3.0e38);
+            if (A.mode == kModeBinned && !ok) {
+                const int cls = m < 128 ? 0 : m < 256 ? 1 : m < 512 ? 2 : 3;
+                const int slot = atomicAdd(&A.book->rescue_count[cls], 1);
+                A.rescue_list[cls * A.rescue_stride + slot] = ridx;
+                if (A.out_status) A.out_status[rec.out] = 1;  // final value written by the FP64 sweep
+            } else if (A.out_status) {
+                A.out_status[rec.out] = ok ? 0 : 3;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// compiled configurations of the FP32 sweep (lanes per pair, rows per lane)
+// ---------------------------------------------------------------------------
+#define PH_FWD32_CONFIGS(X) \
+    X(16, 1) X(16, 2) X(16, 3) X(16, 4) X(16, 5) X(16, 6) X(16, 7) X(16, 8) \
+    X(16, 9) X(16, 10) X(16, 11) X(16, 12) X(16, 13) X(16, 14) X(16, 15) X(16, 16) \
+    X(32, 4) X(32, 6) X(32, 8) X(32, 10) X(32, 12) X(32, 16) \
+    X(64, 2) X(64, 3) X(64, 4) X(64, 5) X(64, 6) X(64, 7) X(64, 8) X(64, 9) X(64, 10) \
+    X(64, 11) X(64, 12) X(64, 13) X(64, 14) X(64, 15) X(64, 16)
+
+bool fwd32_supported(int P, int K)
+{
+#define PH_SUP(p, k) if (P == p && K == k) return true;
+    PH_FWD32_CONFIGS(PH_SUP)
+#undef PH_SUP
+    return false;
+}
+
+// Persistent FP32 sweep over the tiles of one length bin: every wave takes
+// the next tile (one read/haplotype pair per lane group) from the bin's
+// cursor.  Records of a bin are ordered longest haplotype first.
+template <int P, int K>
+__global__ __launch_bounds__(64) void k_fwd32(SweepArgs A, int bin)
+{
+    __shared__ __attribute__((aligned(16))) char lds[Cfg<float, P, K>::LDS_BYTES];
+    Book *bk = A.book;
+    constexpr int G = 64 / P;
+    const int rb = bk->bin_rec_begin[bin], re = bk->bin_rec_begin[bin + 1];
+    const int ntiles = (re - rb + G - 1) / G;
+    int tile = next_tile(&bk->bin_counter[bin]);
+    while (tile < ntiles) {
+        const int first = rb + tile * G;
+        sweep_tile<float, P, K>(A, nullptr, first, min(G, re - first), lds);
+        tile = next_tile(&bk->bin_counter[bin]);
+    }
+}
+
+// Plain FP32 sweep: one pair per wave, pairs in output order, one (64, K).
+template <int K>
+__global__ __launch_bounds__(64) void k_plain32(SweepArgs A)
+{
+    __shared__ __attribute__((aligned(16))) char lds[Cfg<float, 64, K>::LDS_BYTES];
+    int tile = next_tile(&A.book->tile_counter);
+    while (tile < A.plain_count) {
+        sweep_tile<float, 64, K>(A, nullptr, tile, 1, lds);
+        tile = next_tile(&A.book->tile_counter);
+    }
+}
+
+// FP64 sweep over one rescue queue (64 lanes per pair, K rows per lane).
+template <int K>
+__global__ __launch_bounds__(64) void k_fwd64(SweepArgs A)
+{
+    __shared__ __attribute__((aligned(16))) char lds[Cfg<double, 64, K>::LDS_BYTES];
+    const int cls = A.rescue_class;
+    const int count = A.book->rescue_count[cls];
+    const int32_t *list = A.rescue_list + cls * A.rescue_stride;
+    int tile = next_tile(&A.book->rescue_counter[cls]);
+    while (tile < count) {
+        sweep_tile<double, 64, K>(A, list, tile, 1, lds);
+        tile = next_tile(&A.book->rescue_counter[cls]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// binning: counting sort of the pairs by (length bin, haplotype-length bucket)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int pair_key(const BinArgs &a, int64_t k, PairRec &rec)
+{
+    int lo = 0, hi = a.num_batches;  // largest q with out_offset[q] <= k
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (a.out_offset[mid] <= k) lo = mid; else hi = mid;
+    }
+    const int q = lo;
+    const int local = (int)(k - a.out_offset[q]);
+    const int nh = a.batch_hap_begin[q + 1] - a.batch_hap_begin[q];
+    const int r = a.batch_read_begin[q] + local / nh;
+    const int h = a.batch_hap_begin[q] + local % nh;
+    const int m = (int)(a.read_offset[r + 1] - a.read_offset[r]);
+    const int n = (int)(a.hap_offset[h + 1] - a.hap_offset[h]);
+    rec.read = r;
+    rec.hap = h;
+    rec.out = (int)k;
+    rec.n = n;
+    const int b = a.m2bin[m > kMaxReadLen ? kMaxReadLen + 1 : m];
+    const int nb = n < 1024 ? (n >> 4) : 64 + min((n - 1024) >> 7, 63);
+    return b * kBuckets + (kBuckets - 1 - nb);
+}
+
+__global__ __launch_bounds__(256) void k_reset(int32_t *hist, int nkeys, Book *bk)
+{
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < nkeys; i += gridDim.x * 256) hist[i] = 0;
+    if (blockIdx.x == 0) {
+        int32_t *w = (int32_t *)bk;
+        for (int i = threadIdx.x; i < (int)(sizeof(Book) / 4); i += 256) w[i] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
+{
+    __shared__ int h[kMaxKeys];
+    const int nk = a.num_bins * kBuckets;
+    for (int i = threadIdx.x; i < nk; i += 256) h[i] = 0;
+    __syncthreads();
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < a.num_pairs;
+         k += (int64_t)gridDim.x * 256) {
+        PairRec rec;
+        atomicAdd(&h[pair_key(a, k, rec)], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nk; i += 256)
+        if (h[i]) atomicAdd(&a.hist[i], h[i]);
+}
+
+// one block: exclusive scan of the key histogram (in place, becomes the
+// scatter cursors), record and tile ranges of every bin.
+__global__ __launch_bounds__(1024) void k_bin_scan(BinArgs a)
+{
+    __shared__ int part[1024];
+    const int nk = a.num_bins * kBuckets;
+    constexpr int PER = kMaxKeys / 1024;
+    int loc[PER];
+    int sum = 0;
+    for (int j = 0; j < PER; ++j) {
+        int i = threadIdx.x * PER + j;
+        loc[j] = i < nk ? a.hist[i] : 0;
+        sum += loc[j];
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = part[threadIdx.x] - sum;
+    for (int j = 0; j < PER; ++j) {
+        int i = threadIdx.x * PER + j;
+        if (i < nk) {
+            a.hist[i] = run;
+            if (i % kBuckets == 0) a.book->bin_rec_begin[i / kBuckets] = run;
+        }
+        run += loc[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Book *bk = a.book;
+        bk->bin_rec_begin[a.num_bins] = (int)a.num_pairs;
+        int tiles = 0;
+        for (int b = 0; b < a.num_bins; ++b) {
+            bk->bin_tile_begin[b] = tiles;
+            const int cnt = bk->bin_rec_begin[b + 1] - bk->bin_rec_begin[b];
+            const int G = a.bin_G[b];
+            tiles += (cnt + G - 1) / G;
+        }
+        bk->bin_tile_begin[a.num_bins] = tiles;
+    }
+}
+
+constexpr int kScatterPer = 8;  // pairs per thread in the scatter
+
+__global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a)
+{
+    __shared__ int cnt[kMaxKeys];
+    __shared__ int base[kMaxKeys];
+    const int nk = a.num_bins * kBuckets;
+    for (int i = threadIdx.x; i < nk; i += 256) cnt[i] = 0;
+    __syncthreads();
+    PairRec rec[kScatterPer];
+    int key[kScatterPer], rank[kScatterPer];
+    const int64_t first = (int64_t)blockIdx.x * 256 * kScatterPer;
+    for (int j = 0; j < kScatterPer; ++j) {
+        int64_t k = first + (int64_t)j * 256 + threadIdx.x;
+        key[j] = -1;
+        if (k < a.num_pairs) {
+            key[j] = pair_key(a, k, rec[j]);
+            rank[j] = atomicAdd(&cnt[key[j]], 1);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nk; i += 256)
+        if (cnt[i]) base[i] = atomicAdd(&a.hist[i], cnt[i]);
+    __syncthreads();
+    for (int j = 0; j < kScatterPer; ++j)
+        if (key[j] >= 0) a.recs[base[key[j]] + rank[j]] = rec[j];
+}
+
+__global__ __launch_bounds__(256) void k_plain_records(BinArgs a)
+{
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < a.num_pairs;
+         k += (int64_t)gridDim.x * 256) {
+        PairRec rec;
+        pair_key(a, k, rec);
+        a.recs[k] = rec;
+    }
+}
+
+// Explicit-parameter mode: exponentiate the log10 parameters of every read
+// position once per call, [npos][7] float -> [npos][8] double.
+__global__ __launch_bounds__(256) void k_prep_params(const float *lg, int64_t npos, double *lin)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < npos * 8;
+         i += (int64_t)gridDim.x * 256) {
+        const int64_t pos = i >> 3;
+        const int c = (int)(i & 7);
+        lin[i] = c < 7 ? exp10((double)lg[pos * 7 + c]) : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_validate(const uint8_t *rb, int64_t nr, const uint8_t *hb,
+                                                  int64_t nh, Book *bk)
+{
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nr; i += (int64_t)gridDim.x * 256)
+        bad += rb[i] > 4;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nh; i += (int64_t)gridDim.x * 256)
+        bad += hb[i] > 4;
+    if (bad) atomicAdd(&bk->bad_code, bad);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static int grid_for(int64_t items, int per_block, int cap)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_bin_count(const BinArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin_count, dim3(grid_for(a.num_pairs, 256 * 16, 2048)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_scan(const BinArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_scatter(const BinArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(a.num_pairs, 256 * kScatterPer, 1 << 30)),
+                       dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_records(const BinArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_plain_records, dim3(grid_for(a.num_pairs, 256 * 4, 4096)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_keys(int32_t *hist, int nkeys, Book *book, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset, dim3(grid_for(nkeys, 256, 64)), dim3(256), 0, s, hist, nkeys, book);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd32(const SweepArgs &a_in, int P, int K, int bin, int grid, hipStream_t s)
+{
+    SweepArgs a = a_in;
+    a.mode = kModeBinned;
+#define PH_L32(p, k) \
+    if (P == p && K == k) { hipLaunchKernelGGL((k_fwd32<p, k>), dim3(grid), dim3(64), 0, s, a, bin); return hipGetLastError(); }
+    PH_FWD32_CONFIGS(PH_L32)
+#undef PH_L32
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_plain32(const SweepArgs &a_in, int K, int grid, hipStream_t s)
+{
+    SweepArgs a = a_in;
+    a.mode = kModePlain;
+    switch (K) {
+#define PH_PK(k) case k: hipLaunchKernelGGL(k_plain32<k>, dim3(grid), dim3(64), 0, s, a); break;
+        PH_PK(1) PH_PK(2) PH_PK(3) PH_PK(4) PH_PK(5) PH_PK(6) PH_PK(7) PH_PK(8)
+        PH_PK(9) PH_PK(10) PH_PK(11) PH_PK(12) PH_PK(13) PH_PK(14) PH_PK(15) PH_PK(16)
+#undef PH_PK
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static const int kRescueK[kRescueClasses] = {2, 4, 8, 16};
+
+hipError_t launch_fwd64(const SweepArgs &a, int cls, int grid, hipStream_t s)
+{
+    SweepArgs b = a;
+    b.rescue_class = cls;
+    b.mode = kModeRescue;
+    switch (kRescueK[cls]) {
+    case 2: hipLaunchKernelGGL(k_fwd64<2>, dim3(grid), dim3(64), 0, s, b); break;
+    case 4: hipLaunchKernelGGL(k_fwd64<4>, dim3(grid), dim3(64), 0, s, b); break;
+    case 8: hipLaunchKernelGGL(k_fwd64<8>, dim3(grid), dim3(64), 0, s, b); break;
+    case 16: hipLaunchKernelGGL(k_fwd64<16>, dim3(grid), dim3(64), 0, s, b); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_params(const float *lg, int64_t npos, double *lin, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_prep_params, dim3(grid_for(npos * 8, 256 * 4, 8192)), dim3(256), 0, s, lg,
+                       npos, lin);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const DevProblem &pb, int64_t nrb, int64_t nhb, Book *book, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(nrb + nhb, 256 * 8, 4096)), dim3(256), 0, s,
+                       pb.read_bases, nrb, pb.hap_bases, nhb, book);
+    return hipGetLastError();
+}
+
+static int occupancy(const void *fn)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64, 0) != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+int fwd32_blocks_per_cu(int P, int K)
+{
+#define PH_O32(p, k) if (P == p && K == k) return occupancy((const void *)k_fwd32<p, k>);
+    PH_FWD32_CONFIGS(PH_O32)
+#undef PH_O32
+    return 1;
+}
+
+int plain32_blocks_per_cu(int K)
+{
+    switch (K) {
+#define PH_PO(k) case k: return occupancy((const void *)k_plain32<k>);
+        PH_PO(1) PH_PO(2) PH_PO(3) PH_PO(4) PH_PO(5) PH_PO(6) PH_PO(7) PH_PO(8)
+        PH_PO(9) PH_PO(10) PH_PO(11) PH_PO(12) PH_PO(13) PH_PO(14) PH_PO(15) PH_PO(16)
+#undef PH_PO
+    }
+    return 1;
+}
+
+int fwd64_blocks_per_cu(int cls)
+{
+    switch (kRescueK[cls]) {
+    case 2: return occupancy((const void *)k_fwd64<2>);
+    case 4: return occupancy((const void *)k_fwd64<4>);
+    case 8: return occupancy((const void *)k_fwd64<8>);
+    case 16: return occupancy((const void *)k_fwd64<16>);
+    }
+    return 1;
+}
+
+}  // namespace ph

@@ -1,0 +1,87 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol that
+include/ph.h declares, and rejects bad shapes before touching the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2411_11547_amd import binding
+from paper_2411_11547_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ph.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(ph_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_binding_exports():
+    assert set(declared_functions()) == set(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_defaults():
+    assert "gfx950" in binding.ph_version()
+    o = binding.ph_plan_opts_default()
+    assert o.rescue_threshold == pytest.approx(1e-28) and o.use_graph == 1 and o.plain == 0
+
+
+def _plan_status(problem, **kw):
+    shape, keep = binding.shape_of(problem)
+    opts = binding.ph_plan_opts_default()
+    for k, v in kw.items():
+        setattr(opts, k, v)
+    h = ctypes.c_void_p()
+    st = binding.load().ph_plan_create(ctypes.byref(shape), ctypes.byref(opts), ctypes.byref(h))
+    return st, binding.load().ph_last_error().decode()
+
+
+def test_shape_validation_errors():
+    good = wl.from_strings([(["ACGT"], ["ACGTT"])])
+    # empty read
+    bad = wl.from_strings([(["ACGT"], ["ACGTT"])])
+    bad.read_offset[1] = 0
+    bad.read_offset = np.array([0, 0], np.int64)
+    st, msg = _plan_status(bad)
+    assert st == -1 and "length 0" in msg
+    # empty haplotype
+    bad = wl.from_strings([(["ACGT"], ["ACGTT"])])
+    bad.hap_offset = np.array([0, 0], np.int64)
+    st, _ = _plan_status(bad)
+    assert st == -1
+    # read longer than any compiled configuration
+    long = wl.from_strings([(["A" * 1024], ["ACGT"])])
+    st, msg = _plan_status(long)
+    assert st == -2 and "1024" in msg
+    # batch range outside the reads
+    bad = wl.from_strings([(["ACGT"], ["ACGTT"])])
+    bad.batch_read_begin = np.array([0, 2], np.int32)
+    st, _ = _plan_status(bad)
+    assert st == -1
+    # bad force_p
+    st, _ = _plan_status(good, force_p=8)
+    assert st == -1
+    # NULL shape
+    h = ctypes.c_void_p()
+    assert binding.load().ph_plan_create(None, None, ctypes.byref(h)) == -1
+
+
+def test_null_plan_calls():
+    lib = binding.load()
+    assert lib.ph_forward_batch(None, None, None, None, None, None) == -1
+    assert lib.ph_backward_batch(None, None, None, None, None, None) == -1
+    assert lib.ph_validate(None, None, None) == -1
+    ms = (ctypes.c_float * 4)()
+    assert lib.ph_plan_stage_ms(None, ms) == -1
+    lib.ph_plan_destroy(None)

@@ -1,0 +1,211 @@
+"""GPU parity of the HIP forward path against the FP64 oracle.
+
+FP32 results must match within |delta log10 L| <= 1e-3 and FP64-rescued
+results within 1e-9.  Every case calls the C ABI through the binding.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import TOL32, TOL64, binding, check_against_oracle, gpu_forward, oracle, say, wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    binding.load()
+    yield
+
+
+def test_config0_binned_graph():
+    say("config0 binned, graph")
+    prob = wl.config0()
+    got, st = gpu_forward(prob)
+    check_against_oracle(prob, got, st)
+    assert np.all(st == binding.PAIR_FP32)
+
+
+def test_config0_plain():
+    say("config0 plain")
+    prob = wl.config0()
+    got, st = gpu_forward(prob, plain=True, use_graph=False)
+    check_against_oracle(prob, got, st)
+
+
+@pytest.mark.parametrize("force_p", [16, 32, 64])
+def test_lane_groups(force_p):
+    say(f"lane groups P={force_p}")
+    prob = wl.config0()
+    got, st = gpu_forward(prob, force_p=force_p, use_graph=False)
+    check_against_oracle(prob, got, st)
+
+
+def _ragged(seed, lens_m, lens_n):
+    rng = np.random.default_rng(seed)
+    batches = []
+    for m_list, n_list in zip(lens_m, lens_n):
+        reads = ["".join(rng.choice(list("ACGTN"), p=[.245, .245, .245, .245, .02], size=m)) for m in m_list]
+        haps = ["".join(rng.choice(list("ACGT"), size=n)) for n in n_list]
+        batches.append((reads, haps))
+    q = dict(base_q=20, ins_q=45, del_q=45, gcp_q=10)
+    prob = wl.from_strings(batches, **q)
+    # varied qualities per base
+    prob.base_qual[:] = rng.integers(5, 41, size=len(prob.base_qual))
+    prob.ins_qual[:] = rng.integers(20, 46, size=len(prob.ins_qual))
+    prob.del_qual[:] = rng.integers(20, 46, size=len(prob.del_qual))
+    prob.gcp_qual[:] = rng.integers(5, 20, size=len(prob.gcp_qual))
+    return prob
+
+
+def test_ragged_lengths_every_bin():
+    """Reads at every bin edge (15/16, 31/32, ..., 255/256, 319/320, 1023),
+    haplotypes around the 64-column ring chunks, a 1x1 pair and empty
+    batches."""
+    say("ragged lengths")
+    ms = [1, 2, 15, 16, 17, 31, 32, 47, 63, 64, 100, 127, 128, 150, 191, 200, 239, 240, 255, 256,
+          300, 319, 320, 511, 512, 700, 1023]
+    ns = [1, 2, 3, 63, 64, 65, 127, 128, 129, 300, 1000]
+    lens_m = [ms[:9], ms[9:18], ms[18:], [1], [], [5, 7]]
+    lens_n = [ns[:4], ns[3:8], ns[6:], [1], [10, 20], []]
+    prob = _ragged(1, lens_m, lens_n)
+    assert prob.num_pairs == 9 * 4 + 9 * 5 + 9 * 5 + 1
+    for kw in (dict(), dict(use_graph=False), dict(force_p=64, use_graph=False)):
+        got, st = gpu_forward(prob, **kw)
+        check_against_oracle(prob, got, st)
+
+
+def test_ungapped_closed_form_150x300():
+    """Explicit parameters with delta = zeta = 0 and alpha = 1: the result is
+    the ungapped scan (beta_1/n) sum over offsets of the emission product."""
+    say("ungapped closed form")
+    rng = np.random.default_rng(7)
+    m, n = 150, 300
+    reads, haps = [], []
+    for _ in range(4):
+        r = "".join(rng.choice(list("ACGT"), size=m))
+        h = list(rng.choice(list("ACGT"), size=n))
+        off = int(rng.integers(0, n - m))
+        h[off:off + m] = list(r)
+        reads.append(r)
+        haps.append("".join(h))
+    prob = wl.from_strings([(reads, haps)])
+    Q = 10 ** -rng.uniform(1.5, 4, len(prob.read_bases))
+    lin = np.stack([np.ones_like(Q), np.full_like(Q, 0.9), np.zeros_like(Q), np.full_like(Q, 0.1),
+                    np.zeros_like(Q), 1 - Q, Q / 3], 1)
+    with np.errstate(divide="ignore"):
+        lg = np.log10(lin).astype(np.float32)
+    got, st = gpu_forward(prob, log10_params=lg)
+    lin32 = 10.0 ** lg.astype(np.float64)
+    r_idx, h_idx = prob.pair_index()
+    for k in range(prob.num_pairs):
+        rb = prob.read(r_idx[k])[0]
+        hb = prob.hap(h_idx[k])
+        p = lin32[prob.read_offset[r_idx[k]]:prob.read_offset[r_idx[k] + 1]]
+        logs = [np.sum(np.log10(np.where(rb == hb[j0:j0 + m], p[:, 5], p[:, 6]))) for j0 in range(n - m + 1)]
+        top = max(logs)
+        want = math.log10(p[0, 1] / n) + top + math.log10(sum(10 ** (x - top) for x in logs))
+        assert abs(got[k] - want) <= TOL32, (k, got[k], want)
+
+
+def test_explicit_log10_params():
+    say("explicit log10 parameters")
+    prob = wl.config0()
+    rng = np.random.default_rng(3)
+    par = oracle.params_from_phred(prob.base_qual, prob.ins_qual, prob.del_qual, prob.gcp_qual)
+    par *= 10 ** rng.uniform(-0.3, 0.3, par.shape)  # off the Phred manifold
+    lg = np.log10(par).astype(np.float32)
+    got, st = gpu_forward(prob, log10_params=lg)
+    check_against_oracle(prob, got, st, log10_params=lg)
+
+
+def test_config1_reduced_all_pairs():
+    say("config1, 16 regions, all pairs")
+    prob = wl.config1(regions=16)
+    got, st = gpu_forward(prob)
+    check_against_oracle(prob, got, st)
+
+
+def test_config2_reduced_all_pairs():
+    say("config2, 24 regions, all pairs")
+    prob = wl.config2(regions=24)
+    got, st = gpu_forward(prob)
+    check_against_oracle(prob, got, st)
+
+
+def test_config1_full_size_sampled():
+    """512,000 pairs in the launch configuration the benchmark times; 1,500
+    sampled outputs checked one by one against the oracle."""
+    say("config1 full size, sampled")
+    prob = wl.config1()
+    got, st = gpu_forward(prob)
+    assert np.all(np.isfinite(got))
+    idx = np.random.default_rng(11).choice(prob.num_pairs, 1500, replace=False)
+    check_against_oracle(prob, got, st, pairs=idx)
+
+
+def test_rescue_path_config3_subset():
+    say("config3 subset: FP32 + FP64 rescue")
+    prob = wl.config3(pairs=300)
+    got, st = gpu_forward(prob)
+    err = check_against_oracle(prob, got, st)
+    assert (st == binding.PAIR_FP64).any(), "precision stress should send some pairs to FP64"
+
+
+def test_forced_rescue_all_fp64():
+    say("forced rescue: every pair in FP64")
+    prob = _ragged(5, [[1, 40, 150, 250, 300, 600]], [[1, 70, 400]])
+    got, st = gpu_forward(prob, rescue_threshold=math.inf)
+    assert np.all(st == binding.PAIR_FP64)
+    check_against_oracle(prob, got, st)
+
+
+def test_graph_replay_bitwise():
+    """Replays of the captured graph, with other GPU work in between, give
+    bitwise-identical results."""
+    import torch
+    say("graph replay")
+    prob = wl.config2(regions=6)
+    dev = binding.DeviceProblem(prob)
+    plan = binding.Plan(prob)
+    outs = []
+    for i in range(3):
+        out, st = plan.forward(dev)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy().copy())
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+    plan.close()
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+    eager, _ = gpu_forward(prob, use_graph=False)
+    assert np.array_equal(outs[0], eager)
+
+
+def test_validate_rejects_bad_codes():
+    import torch
+    say("validate")
+    prob = wl.config0()
+    prob.hap_bases[7] = 9
+    dev = binding.DeviceProblem(prob)
+    plan = binding.Plan(prob)
+    with pytest.raises(binding.PHError) as e:
+        plan.validate(dev)
+    assert e.value.status == -1
+    prob.hap_bases[7] = 2
+    dev2 = binding.DeviceProblem(prob)
+    plan.validate(dev2)
+    plan.close()
+
+
+def test_plan_mismatch():
+    say("plan mismatch")
+    a, b = wl.config0(), wl.config1(regions=1)
+    plan = binding.Plan(a)
+    dev = binding.DeviceProblem(b)
+    with pytest.raises(binding.PHError) as e:
+        plan.forward(dev)
+    assert e.value.status == -5
+    plan.close()
