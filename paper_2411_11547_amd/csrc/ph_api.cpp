@@ -136,8 +136,8 @@ struct ph_plan {
     hipEvent_t ev[kStageEvents] = {};
     bool stages_recorded = false;
 
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[3] = {};
+    hipGraphExec_t exec[3] = {};
     std::vector<const void *> graph_key;
 
     hipStream_t last_stream = nullptr;
@@ -149,8 +149,10 @@ namespace {
 void free_plan(ph_plan *p)
 {
     if (!p) return;
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (int i = 0; i < 3; ++i) {
+        if (p->exec[i]) (void)hipGraphExecDestroy(p->exec[i]);
+        if (p->graph[i]) (void)hipGraphDestroy(p->graph[i]);
+    }
     void *bufs[] = {p->d_out_offset, p->d_m2bin, p->d_bin_G, p->d_hist, p->d_recs, p->d_book, p->d_rescue, p->d_lin};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -395,57 +397,62 @@ SweepArgs sweep_args(ph_plan *p, const ph_problem *pb, const double *lin, double
     return a;
 }
 
-// Enqueue the whole forward sequence on stream s.
-ph_status enqueue_forward(ph_plan *p, const ph_problem *pb, const float *log10_params, double *out,
-                          uint8_t *status, hipStream_t s)
+// Enqueue one stage of the forward sequence on stream s:
+//   0 = parameter exponentiation (explicit mode) and binning,
+//   1 = FP32 sweeps of all bins, 2 = FP64 rescue sweeps.
+ph_status enqueue_stage(ph_plan *p, int stage, const ph_problem *pb, const float *log10_params, double *out,
+                        uint8_t *status, hipStream_t s)
 {
-    const double *lin = nullptr;
-    HIPCHK(hipEventRecord(p->ev[0], s));
-    if (log10_params) {
-        HIPCHK(launch_prep_params(log10_params, p->nread_bases, p->d_lin, s));
-        lin = p->d_lin;
-    }
-    const BinArgs ba = bin_args(p, pb);
-    const int nkeys = ba.num_bins * kBuckets;
-    HIPCHK(launch_reset_keys(p->d_hist, nkeys, p->d_book, s));
-    if (p->opts.plain) {
-        HIPCHK(launch_plain_records(ba, s));
-    } else {
-        HIPCHK(launch_bin_count(ba, s));
-        HIPCHK(launch_bin_scan(ba, s));
-        HIPCHK(launch_bin_scatter(ba, s));
-    }
-    HIPCHK(hipEventRecord(p->ev[1], s));
+    const double *lin = log10_params ? p->d_lin : nullptr;
     const SweepArgs sa = sweep_args(p, pb, lin, out, status);
-    if (p->opts.plain) {
-        HIPCHK(launch_plain32(sa, p->plain_K, p->plain_grid, s));
-    } else {
-        // bins longest first, round-robin over side streams forked from s
-        HIPCHK(hipEventRecord(p->fork, s));
-        bool used[kSideStreams] = {};
-        int next = 0;
-        for (int b = 0; b < sa.num_bins; ++b) {
-            if (!p->bin_grid[b]) continue;
-            const int k = next++ % kSideStreams;
-            if (!used[k]) {
-                HIPCHK(hipStreamWaitEvent(p->side[k], p->fork, 0));
-                used[k] = true;
+    if (stage == 0) {
+        if (log10_params) HIPCHK(launch_prep_params(log10_params, p->nread_bases, p->d_lin, s));
+        const BinArgs ba = bin_args(p, pb);
+        HIPCHK(launch_reset_keys(p->d_hist, ba.num_bins * kBuckets, p->d_book, s));
+        if (p->opts.plain) {
+            HIPCHK(launch_plain_records(ba, s));
+        } else {
+            HIPCHK(launch_bin_count(ba, s));
+            HIPCHK(launch_bin_scan(ba, s));
+            HIPCHK(launch_bin_scatter(ba, s));
+        }
+    } else if (stage == 1) {
+        if (p->opts.plain) {
+            HIPCHK(launch_plain32(sa, p->plain_K, p->plain_grid, s));
+        } else {
+            // bins longest first, round-robin over side streams forked from s
+            HIPCHK(hipEventRecord(p->fork, s));
+            bool used[kSideStreams] = {};
+            int next = 0;
+            for (int b = 0; b < sa.num_bins; ++b) {
+                if (!p->bin_grid[b]) continue;
+                const int k = next++ % kSideStreams;
+                if (!used[k]) {
+                    HIPCHK(hipStreamWaitEvent(p->side[k], p->fork, 0));
+                    used[k] = true;
+                }
+                HIPCHK(launch_fwd32(sa, sa.bins[b].P, sa.bins[b].K, b, p->bin_grid[b], p->side[k]));
             }
-            HIPCHK(launch_fwd32(sa, sa.bins[b].P, sa.bins[b].K, b, p->bin_grid[b], p->side[k]));
+            for (int k = 0; k < kSideStreams; ++k) {
+                if (!used[k]) continue;
+                HIPCHK(hipEventRecord(p->join[k], p->side[k]));
+                HIPCHK(hipStreamWaitEvent(s, p->join[k], 0));
+            }
         }
-        for (int k = 0; k < kSideStreams; ++k) {
-            if (!used[k]) continue;
-            HIPCHK(hipEventRecord(p->join[k], p->side[k]));
-            HIPCHK(hipStreamWaitEvent(s, p->join[k], 0));
-        }
-    }
-    HIPCHK(hipEventRecord(p->ev[2], s));
-    if (!p->opts.plain) {
+    } else if (!p->opts.plain) {
         for (int c = 0; c < kRescueClasses; ++c)
             if (p->rescue_grid[c]) HIPCHK(launch_fwd64(sa, c, p->rescue_grid[c], s));
     }
-    HIPCHK(hipEventRecord(p->ev[3], s));
     return PH_OK;
+}
+
+void drop_graphs(ph_plan *p)
+{
+    for (int i = 0; i < 3; ++i) {
+        if (p->exec[i]) { (void)hipGraphExecDestroy(p->exec[i]); p->exec[i] = nullptr; }
+        if (p->graph[i]) { (void)hipGraphDestroy(p->graph[i]); p->graph[i] = nullptr; }
+    }
+    p->graph_key.clear();
 }
 
 }  // namespace
@@ -469,33 +476,43 @@ ph_status ph_forward_batch(ph_plan *p, const ph_problem *pb, const float *log10_
         p->d_lin = nullptr;
         if ((st = dalloc(&p->d_lin, (size_t)p->nread_bases * 8))) return st;
         p->lin_cap = p->nread_bases;
-        if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
-        if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
-        p->graph_key.clear();
+        drop_graphs(p);
     }
 
+    // Each stage is captured into its own graph so that HIP events recorded on
+    // the caller's stream between the three launches time the stages.
     if (p->opts.use_graph) {
         std::vector<const void *> key = {pb->batch_read_begin, pb->batch_hap_begin, pb->read_offset,
                                          pb->read_bases, pb->base_qual, pb->ins_qual, pb->del_qual,
                                          pb->gcp_qual, pb->hap_offset, pb->hap_bases, log10_params,
                                          out_log10L, out_status};
-        if (!p->exec || key != p->graph_key) {
-            if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
-            if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
-            HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
-            st = enqueue_forward(p, pb, log10_params, out_log10L, out_status, p->cap);
-            hipGraph_t g = nullptr;
-            hipError_t e = hipStreamEndCapture(p->cap, &g);
-            if (st != PH_OK) { if (g) (void)hipGraphDestroy(g); return st; }
-            if (e != hipSuccess) return fail(PH_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-            p->graph = g;
-            HIPCHK(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0));
+        if (!p->exec[0] || key != p->graph_key) {
+            drop_graphs(p);
+            for (int stage = 0; stage < 3; ++stage) {
+                HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
+                st = enqueue_stage(p, stage, pb, log10_params, out_log10L, out_status, p->cap);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(p->cap, &g);
+                if (st != PH_OK) { if (g) (void)hipGraphDestroy(g); drop_graphs(p); return st; }
+                if (e != hipSuccess) { drop_graphs(p); return fail(PH_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e)); }
+                p->graph[stage] = g;
+                e = hipGraphInstantiate(&p->exec[stage], g, nullptr, nullptr, 0);
+                if (e != hipSuccess) { drop_graphs(p); return fail(PH_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e)); }
+            }
             p->graph_key = key;
         }
-        HIPCHK(hipGraphLaunch(p->exec, s));
+        for (int stage = 0; stage < 3; ++stage) {
+            HIPCHK(hipEventRecord(p->ev[stage], s));
+            HIPCHK(hipGraphLaunch(p->exec[stage], s));
+        }
+        HIPCHK(hipEventRecord(p->ev[3], s));
     } else {
-        st = enqueue_forward(p, pb, log10_params, out_log10L, out_status, s);
-        if (st != PH_OK) return st;
+        for (int stage = 0; stage < 3; ++stage) {
+            HIPCHK(hipEventRecord(p->ev[stage], s));
+            st = enqueue_stage(p, stage, pb, log10_params, out_log10L, out_status, s);
+            if (st != PH_OK) return st;
+        }
+        HIPCHK(hipEventRecord(p->ev[3], s));
     }
     p->last_stream = s;
     p->stages_recorded = true;

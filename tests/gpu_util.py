@@ -34,21 +34,30 @@ def gpu_forward(prob, log10_params=None, **plan_kw):
     return res
 
 
+FLOOR_LOG10 = -608.0  # FP64 sweep range floor: scaled sum 2^-1000 at scale 2^1020
+
+
 def check_against_oracle(prob, got, status, ref=None, log10_params=None, pairs=None):
-    """Elementwise comparison, FP32 pairs to TOL32 and FP64 pairs to TOL64."""
+    """Elementwise comparison: FP32 pairs to TOL32, FP64 pairs to TOL64.
+    Pairs below the FP64 sweep's range must carry the floor status (and only
+    those); their value is not compared."""
     if ref is None:
         ref = oracle.forward(prob, log10_params=log10_params, pairs=pairs)
     if pairs is not None:
         got, status = got[pairs], status[pairs]
-    err = np.abs(got - ref)
-    fin = np.isfinite(ref)
-    assert np.all(np.isfinite(got[fin])), "non-finite GPU result where the oracle is finite"
     s32 = status == binding.PAIR_FP32
     s64 = status == binding.PAIR_FP64
-    assert np.all(s32 | s64), f"unexpected status values {np.unique(status)}"
+    s2 = status == binding.PAIR_FP64_FLOOR
+    assert np.all(s32 | s64 | s2), f"unexpected status values {np.unique(status)}"
+    assert np.all(ref[s2] < FLOOR_LOG10 + 8), "floor status on a pair inside the FP64 range"
+    assert np.all(s2[ref < FLOOR_LOG10 - 12]), "pair below the FP64 range without the floor status"
+    cmp = s32 | s64
+    assert np.all(np.isfinite(got[cmp])), "non-finite GPU result where a value is expected"
+    err = np.abs(got - ref)
     e32 = float(err[s32].max()) if s32.any() else 0.0
     e64 = float(err[s64].max()) if s64.any() else 0.0
-    say(f"  pairs={len(ref)} fp32={int(s32.sum())} max|d|={e32:.3e} fp64={int(s64.sum())} max|d|={e64:.3e}")
+    say(f"  pairs={len(ref)} fp32={int(s32.sum())} max|d|={e32:.3e} fp64={int(s64.sum())} "
+        f"max|d|={e64:.3e} floor={int(s2.sum())}")
     assert e32 <= TOL32, e32
     assert e64 <= TOL64, e64
     return err

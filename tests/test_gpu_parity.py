@@ -44,16 +44,35 @@ def test_lane_groups(force_p):
     check_against_oracle(prob, got, st)
 
 
-def _ragged(seed, lens_m, lens_n):
+def _ragged(seed, lens_m, lens_n, related=True):
+    """Batches with the given read and haplotype lengths.  related=True makes
+    haplotypes mutated copies of one reference and reads error-bearing
+    copies of haplotype stretches (extended with random bases when longer
+    than the haplotype), so likelihoods stay in the range real data has."""
     rng = np.random.default_rng(seed)
     batches = []
     for m_list, n_list in zip(lens_m, lens_n):
-        reads = ["".join(rng.choice(list("ACGTN"), p=[.245, .245, .245, .245, .02], size=m)) for m in m_list]
-        haps = ["".join(rng.choice(list("ACGT"), size=n)) for n in n_list]
-        batches.append((reads, haps))
-    q = dict(base_q=20, ins_q=45, del_q=45, gcp_q=10)
-    prob = wl.from_strings(batches, **q)
-    # varied qualities per base
+        ref = rng.choice(list("ACGT"), size=max(n_list + [1]) + 8)
+        haps = []
+        for n in n_list:
+            h = ref[:n].copy() if related else rng.choice(list("ACGT"), size=n)
+            flip = rng.random(n) < 0.02
+            h[flip] = rng.choice(list("ACGT"), size=int(flip.sum()))
+            haps.append(h)
+        reads = []
+        for m in m_list:
+            if related and haps:
+                h = haps[int(rng.integers(0, len(haps)))]
+                s0 = int(rng.integers(0, max(1, len(h) - m + 1)))
+                r = list(h[s0:s0 + m]) + list(rng.choice(list("ACGT"), size=max(0, m - len(h))))
+                r = np.array(r[:m])
+            else:
+                r = rng.choice(list("ACGT"), size=m)
+            err = rng.random(m) < 0.02
+            r[err] = rng.choice(list("ACGTN"), size=int(err.sum()))
+            reads.append("".join(r))
+        batches.append((reads, ["".join(h) for h in haps]))
+    prob = wl.from_strings(batches)
     prob.base_qual[:] = rng.integers(5, 41, size=len(prob.base_qual))
     prob.ins_qual[:] = rng.integers(20, 46, size=len(prob.ins_qual))
     prob.del_qual[:] = rng.integers(20, 46, size=len(prob.del_qual))
@@ -61,21 +80,39 @@ def _ragged(seed, lens_m, lens_n):
     return prob
 
 
+RAGGED_M = [1, 2, 15, 16, 17, 31, 32, 47, 63, 64, 100, 127, 128, 150, 191, 200, 239, 240, 255, 256,
+            300, 319, 320, 511, 512, 700, 1023]
+RAGGED_N = [1, 2, 3, 63, 64, 65, 127, 128, 129, 300, 1000, 1100]
+
+
 def test_ragged_lengths_every_bin():
     """Reads at every bin edge (15/16, 31/32, ..., 255/256, 319/320, 1023),
     haplotypes around the 64-column ring chunks, a 1x1 pair and empty
-    batches."""
+    batches, through the default bins, the eager path and 64-lane groups."""
     say("ragged lengths")
-    ms = [1, 2, 15, 16, 17, 31, 32, 47, 63, 64, 100, 127, 128, 150, 191, 200, 239, 240, 255, 256,
-          300, 319, 320, 511, 512, 700, 1023]
-    ns = [1, 2, 3, 63, 64, 65, 127, 128, 129, 300, 1000]
+    ms, ns = RAGGED_M, RAGGED_N
     lens_m = [ms[:9], ms[9:18], ms[18:], [1], [], [5, 7]]
-    lens_n = [ns[:4], ns[3:8], ns[6:], [1], [10, 20], []]
+    lens_n = [ns[:4], ns[3:8], ns[7:], [1], [10, 20], []]
     prob = _ragged(1, lens_m, lens_n)
     assert prob.num_pairs == 9 * 4 + 9 * 5 + 9 * 5 + 1
+    ref = oracle.forward(prob)
     for kw in (dict(), dict(use_graph=False), dict(force_p=64, use_graph=False)):
         got, st = gpu_forward(prob, **kw)
-        check_against_oracle(prob, got, st)
+        check_against_oracle(prob, got, st, ref=ref)
+
+
+def test_fp64_floor_status():
+    """Unrelated 500-1023 base reads against random haplotypes fall below the
+    FP64 sweep's range (scaled sum < 2^-1000, log10 L below about -608):
+    those pairs and only those are flagged PH_PAIR_FP64_FLOOR; the rest
+    stay within tolerance."""
+    say("FP64 floor")
+    prob = _ragged(2, [[64, 300, 511, 700, 1023]], [[100, 700, 1100]], related=False)
+    ref = oracle.forward(prob)
+    got, st = gpu_forward(prob)
+    assert (ref < -650).any() and (ref > -500).any()
+    check_against_oracle(prob, got, st, ref=ref)
+    assert (st == binding.PAIR_FP64_FLOOR).any()
 
 
 def test_ungapped_closed_form_150x300():
@@ -157,9 +194,9 @@ def test_rescue_path_config3_subset():
 
 def test_forced_rescue_all_fp64():
     say("forced rescue: every pair in FP64")
-    prob = _ragged(5, [[1, 40, 150, 250, 300, 600]], [[1, 70, 400]])
+    prob = _ragged(5, [[1, 40, 150, 250, 300, 600]], [[1, 70, 400, 700]])
     got, st = gpu_forward(prob, rescue_threshold=math.inf)
-    assert np.all(st == binding.PAIR_FP64)
+    assert np.all((st == binding.PAIR_FP64) | (st == binding.PAIR_FP64_FLOOR))
     check_against_oracle(prob, got, st)
 
 
