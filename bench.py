@@ -55,6 +55,38 @@ def time_forward(plan, dev, steps, warmup, stage=True):
     return (t1 - t0) / steps, np.array(stages) if stages else None
 
 
+ADJ_FLOPS_PER_CELL = 37  # 11 recompute + 11 adjoint + 15 gradient accumulation (FP32)
+
+
+def time_adjoint(steps):
+    """Backward pass (checkpointed forward + reverse sweep + gradients) on
+    the adjoint workload: 10,000 pairs, 150 bp reads x 200-600 bp haplotypes."""
+    import torch
+    from paper_2411_11547_amd import binding, workloads as wl
+    prob = wl.config4()
+    dev = binding.DeviceProblem(prob)
+    plan = binding.Plan(prob, keep_checkpoints=True)
+    u = torch.ones(prob.num_pairs, dtype=torch.float64, device="cuda")
+    grad = torch.empty((int(prob.read_offset[-1]), 7), dtype=torch.float32, device="cuda")
+    plan.backward(dev, u, grad_params=grad)
+    torch.cuda.synchronize()
+    ms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.backward(dev, u, grad_params=grad)
+        ms.append(plan.stage_ms()[3])
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    plan.close()
+    cells = prob.total_cells
+    kms = float(np.mean(ms))
+    log(f"adjoint: {sec * 1e3:.3f} ms/step, {cells / sec / 1e9:.1f} GCUPS (stage {kms:.3f} ms)")
+    return {"workload": prob.name, "pairs": prob.num_pairs, "cells": cells, "ms_per_step": round(sec * 1e3, 4),
+            "gcups": round(cells / sec / 1e9, 2), "stage_ms": round(kms, 4),
+            "fp32_tflops": round(ADJ_FLOPS_PER_CELL * cells / (kms * 1e-3) / 1e12, 3),
+            "frac_fp32_peak": round(ADJ_FLOPS_PER_CELL * cells / (kms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)}
+
+
 def cpu_baseline(prob, target_cells=2.0e10, seed=0):
     import oracle
     r_idx, h_idx = prob.pair_index()
@@ -81,6 +113,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune-table", default=None)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=5)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -125,6 +159,8 @@ def main():
             "kernel_ms": round(float(st_mean[1]), 4),
             "valu_slot_frac": round(VALU_PER_CELL * cells / t32 / PEAK_VALU_LANE_OPS, 4)}
 
+    adj = None if args.no_adjoint else time_adjoint(args.adjoint_steps)
+
     cpu = None if args.no_cpu else cpu_baseline(prob)
     if cpu:
         log(f"cpu oracle: {cpu['value']} GCUPS on {cpu['cores']} threads")
@@ -140,7 +176,8 @@ def main():
            "rescued_pairs": int(rescued),
            "stage_ms": {"binning": round(float(st_mean[0]), 4), "fp32_sweep": round(float(st_mean[1]), 4),
                         "fp64_rescue": round(float(st_mean[2]), 4)},
-           "adjoint_gcups": None,
+           "adjoint_gcups": None if adj is None else adj["gcups"],
+           "adjoint": adj,
            "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 

@@ -210,6 +210,7 @@ class Plan:
         self._tune = tune_table.encode() if tune_table else None
         opts.tune_table_path = self._tune
         shape, self._keep = shape_of(problem)
+        self.problem_bases = int(problem.read_offset[-1])
         self.handle = ph_plan_create(shape, opts)
         self.num_pairs, self.num_cells, self.max_read_len, self.max_hap_len = ph_plan_info(self.handle)
 
@@ -223,6 +224,20 @@ class Plan:
         ph_forward_batch(self.handle, dev.c, lp, ctypes.c_void_p(out.data_ptr()),
                          ctypes.c_void_p(status.data_ptr()), stream or current_stream())
         return out[:self.num_pairs], status[:self.num_pairs]
+
+    def backward(self, dev: DeviceProblem, grad_log10L, log10_params=None, grad_params=None, stream=None):
+        """Gradient of sum_p grad_log10L[p] * log10 L_p w.r.t. the log10
+        parameters of every read base: float32 [sum m, 7]."""
+        torch = _torch()
+        nb = int(self.problem_bases)
+        if grad_params is None:
+            grad_params = torch.empty((max(nb, 1), 7), dtype=torch.float32, device="cuda")
+        g = grad_log10L.contiguous()
+        assert g.dtype == torch.float64 and g.numel() >= self.num_pairs
+        lp = None if log10_params is None else ctypes.c_void_p(log10_params.data_ptr())
+        ph_backward_batch(self.handle, dev.c, lp, ctypes.c_void_p(g.data_ptr()),
+                          ctypes.c_void_p(grad_params.data_ptr()), stream or current_stream())
+        return grad_params[:nb]
 
     def validate(self, dev: DeviceProblem, stream=None):
         ph_validate(self.handle, dev.c, stream or current_stream())

@@ -63,6 +63,10 @@ constexpr int kStageEvents = 5;
 
 std::once_flag g_lut_once;
 hipError_t g_lut_status = hipSuccess;
+std::once_flag g_lut_adj_once;
+hipError_t g_lut_adj_status = hipSuccess;
+
+constexpr int64_t kAdjWsFloats = (int64_t)1 << 29;  // 2 GiB of checkpoints per chunk
 
 int rescue_class_of(int m) { return m < 128 ? 0 : m < 256 ? 1 : m < 512 ? 2 : 3; }
 
@@ -142,6 +146,27 @@ struct ph_plan {
 
     hipStream_t last_stream = nullptr;
     bool forward_done = false;
+
+    // host copy of the shape (adjoint tables are built from it on demand)
+    std::vector<int32_t> h_rb, h_hb;
+    std::vector<int64_t> h_ro, h_ho, h_out_off;
+
+    // adjoint: records grouped by (P, K), tiled, cut into chunks whose
+    // checkpoints fit the workspace
+    struct AdjChunk {
+        int P, K;
+        int64_t rec_begin;
+        int32_t nrec, tiles, hs_bytes;
+    };
+    bool adj_built = false;
+    ph_status adj_status = PH_OK;
+    std::string adj_error;
+    std::vector<AdjChunk> adj_chunks;
+    AdjRec *d_adj_recs = nullptr;
+    double *d_adj_Ls = nullptr;
+    float *d_ws = nullptr;
+    hipEvent_t ev_adj[2] = {};
+    bool adj_recorded = false;
 };
 
 namespace {
@@ -153,7 +178,10 @@ void free_plan(ph_plan *p)
         if (p->exec[i]) (void)hipGraphExecDestroy(p->exec[i]);
         if (p->graph[i]) (void)hipGraphDestroy(p->graph[i]);
     }
-    void *bufs[] = {p->d_out_offset, p->d_m2bin, p->d_bin_G, p->d_hist, p->d_recs, p->d_book, p->d_rescue, p->d_lin};
+    void *bufs[] = {p->d_out_offset, p->d_m2bin, p->d_bin_G, p->d_hist, p->d_recs, p->d_book, p->d_rescue, p->d_lin,
+                    p->d_adj_recs, p->d_adj_Ls, p->d_ws};
+    for (auto &e : p->ev_adj)
+        if (e) (void)hipEventDestroy(e);
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &e : p->ev)
@@ -186,6 +214,113 @@ ph_status check_problem(const ph_plan *p, const ph_problem *pb)
     if (!pb->batch_read_begin || !pb->batch_hap_begin || !pb->read_offset || !pb->hap_offset ||
         !pb->read_bases || !pb->hap_bases)
         return fail(PH_ERR_INVALID, "problem has a NULL array");
+    return PH_OK;
+}
+
+// Adjoint configuration of a read length: 32 lanes x K <= 5 rows, then 64 x K.
+bool adj_config(int m, int &P, int &K)
+{
+    if (m + 1 <= 32 * 5) {
+        P = 32;
+        K = (m + 1 + 31) / 32;
+    } else if (m + 1 <= 64 * 5) {
+        P = 64;
+        K = std::max(3, (m + 1 + 63) / 64);
+    } else {
+        return false;
+    }
+    return adj_supported(P, K);
+}
+
+ph_status build_adjoint(ph_plan *p)
+{
+    if (p->adj_built) return p->adj_status;
+    p->adj_built = true;
+    struct Item {
+        AdjRec r;
+        int P, K;
+    };
+    std::vector<Item> items;
+    items.reserve((size_t)p->P);
+    for (int32_t q = 0; q < p->nb; ++q) {
+        const int32_t H = p->h_hb[q + 1] - p->h_hb[q];
+        for (int32_t r = p->h_rb[q]; r < p->h_rb[q + 1]; ++r) {
+            const int m = (int)(p->h_ro[r + 1] - p->h_ro[r]);
+            int P = 0, K = 0;
+            if (!adj_config(m, P, K)) {
+                p->adj_status = PH_ERR_UNSUPPORTED;
+                p->adj_error = "adjoint supports reads up to 319 bases";
+                return p->adj_status;
+            }
+            for (int32_t h = p->h_hb[q]; h < p->h_hb[q + 1]; ++h) {
+                Item it{};
+                it.r.read = r;
+                it.r.hap = h;
+                it.r.out = (int32_t)(p->h_out_off[q] + (int64_t)(r - p->h_rb[q]) * H + (h - p->h_hb[q]));
+                it.r.n = (int32_t)(p->h_ho[h + 1] - p->h_ho[h]);
+                it.P = P;
+                it.K = K;
+                items.push_back(it);
+            }
+        }
+    }
+    // configuration, then longest haplotype first
+    std::sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
+        if (a.P != b.P) return a.P > b.P;
+        if (a.K != b.K) return a.K > b.K;
+        if (a.r.n != b.r.n) return a.r.n > b.r.n;
+        return a.r.out < b.r.out;
+    });
+    std::vector<AdjRec> recs(items.size());
+    size_t i = 0;
+    int64_t ws_max = 0;
+    while (i < items.size()) {
+        const int P = items[i].P, K = items[i].K, G = 64 / P;
+        size_t end = i;
+        while (end < items.size() && items[end].P == P && items[end].K == K) ++end;
+        // tiles of G records, chunks bounded by the workspace size
+        ph_plan::AdjChunk ch{P, K, (int64_t)i, 0, 0, 0};
+        int64_t ws = 0;
+        for (size_t a = i; a < end; a += G) {
+            const size_t b = std::min(end, a + G);
+            const int S = ((items[a].r.n + P - 1 + kAdjC - 1) / kAdjC) * kAdjC;
+            const int64_t per = ((int64_t)(S + 1) * 3 + (int64_t)(S / kAdjC) * 3 * K) * P;
+            if (ch.tiles > 0 && ws + per * (int64_t)(b - a) > kAdjWsFloats) {
+                p->adj_chunks.push_back(ch);
+                ws_max = std::max(ws_max, ws);
+                ch = ph_plan::AdjChunk{P, K, (int64_t)a, 0, 0, 0};
+                ws = 0;
+            }
+            for (size_t k = a; k < b; ++k) {
+                AdjRec &r = recs[k];
+                r = items[k].r;
+                r.S = S;
+                r.ws_off = ws;
+                ws += per;
+            }
+            ch.nrec += (int32_t)(b - a);
+            ch.tiles += 1;
+            const int hsb = ((S + P + 2 + 15) / 16) * 16;
+            ch.hs_bytes = std::max(ch.hs_bytes, hsb);
+        }
+        p->adj_chunks.push_back(ch);
+        ws_max = std::max(ws_max, ws);
+        i = end;
+    }
+    for (const auto &ch : p->adj_chunks) {
+        const int64_t lds = (int64_t)adj_e_bytes(ch.P, ch.K) + (int64_t)(64 / ch.P) * ch.hs_bytes;
+        if (lds > 64 * 1024) {
+            p->adj_status = PH_ERR_UNSUPPORTED;
+            p->adj_error = "haplotype too long for the adjoint sweep";
+            return p->adj_status;
+        }
+    }
+    ph_status st;
+    if ((st = dalloc(&p->d_adj_recs, recs.size()))) return p->adj_status = st;
+    if ((st = dalloc(&p->d_adj_Ls, recs.size()))) return p->adj_status = st;
+    if ((st = dalloc(&p->d_ws, (size_t)std::max<int64_t>(ws_max, 1)))) return p->adj_status = st;
+    hipError_t e = hipMemcpy(p->d_adj_recs, recs.data(), recs.size() * sizeof(AdjRec), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return p->adj_status = fail(PH_ERR_HIP, "hipMemcpy: %s", hipGetErrorString(e));
     return PH_OK;
 }
 
@@ -327,6 +462,20 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     HIPCHK(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
     for (auto &e : p->join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     for (auto &e : p->ev) HIPCHK(hipEventCreate(&e));
+    for (auto &e : p->ev_adj) HIPCHK(hipEventCreate(&e));
+    if (nb > 0) {
+        p->h_rb.assign(rb, rb + nb + 1);
+        p->h_hb.assign(hb, hb + nb + 1);
+    }
+    p->h_ro.assign(ro, ro + nr + 1);
+    p->h_ho.assign(ho, ho + nh + 1);
+    p->h_out_off = out_off;
+    std::call_once(g_lut_adj_once, [] { g_lut_adj_status = upload_luts_adjoint(); });
+    HIPCHK(g_lut_adj_status);
+    if (opts.keep_checkpoints) {
+        ph_status ast = build_adjoint(p.get());
+        if (ast != PH_OK && ast != PH_ERR_UNSUPPORTED) return ast;
+    }
     *out = p.release();
     return PH_OK;
 }
@@ -521,12 +670,54 @@ ph_status ph_forward_batch(ph_plan *p, const ph_problem *pb, const float *log10_
 }
 
 ph_status ph_backward_batch(ph_plan *p, const ph_problem *pb, const float *log10_params,
-                            const double *grad_log10L, float *grad_params, void *stream)
+                            const double *grad_log10L, float *grad_params, void *stream_v)
 {
-    (void)pb; (void)log10_params; (void)grad_log10L; (void)grad_params; (void)stream;
     g_err.clear();
     if (!p) return fail(PH_ERR_INVALID, "plan is NULL");
-    return fail(PH_ERR_UNSUPPORTED, "adjoint sweep not available in this build");
+    ph_status st = check_problem(p, pb);
+    if (st != PH_OK) return st;
+    if (p->P == 0) return PH_OK;
+    if (!grad_log10L || !grad_params) return fail(PH_ERR_INVALID, "gradient buffers are NULL");
+    if (!log10_params && (!pb->base_qual || !pb->ins_qual || !pb->del_qual || !pb->gcp_qual))
+        return fail(PH_ERR_INVALID, "Phred arrays are NULL and no log10 parameters were given");
+    st = build_adjoint(p);
+    if (st != PH_OK) return p->adj_error.empty() ? st : fail(st, "%s", p->adj_error.c_str());
+    hipStream_t s = (hipStream_t)stream_v;
+    if (log10_params && p->lin_cap < p->nread_bases) {
+        if (p->d_lin) HIPCHK(hipFree(p->d_lin));
+        p->d_lin = nullptr;
+        if ((st = dalloc(&p->d_lin, (size_t)p->nread_bases * 8))) return st;
+        p->lin_cap = p->nread_bases;
+        drop_graphs(p);
+    }
+    HIPCHK(hipEventRecord(p->ev_adj[0], s));
+    if (log10_params) HIPCHK(launch_prep_params(log10_params, p->nread_bases, p->d_lin, s));
+    HIPCHK(launch_zero_f32(grad_params, p->nread_bases * 7, s));
+    AdjArgs a{};
+    a.pb.read_offset = pb->read_offset;
+    a.pb.read_bases = pb->read_bases;
+    a.pb.bq = pb->base_qual;
+    a.pb.iq = pb->ins_qual;
+    a.pb.dq = pb->del_qual;
+    a.pb.gq = pb->gcp_qual;
+    a.pb.hap_offset = pb->hap_offset;
+    a.pb.hap_bases = pb->hap_bases;
+    a.lin_params = log10_params ? p->d_lin : nullptr;
+    a.ws = p->d_ws;
+    a.grad_in = grad_log10L;
+    a.grad_out = grad_params;
+    a.threshold = p->threshold;
+    for (const auto &ch : p->adj_chunks) {
+        a.recs = p->d_adj_recs + ch.rec_begin;
+        a.Ls = p->d_adj_Ls + ch.rec_begin;
+        a.nrec = ch.nrec;
+        a.hs_bytes = ch.hs_bytes;
+        HIPCHK(launch_adj(a, ch.P, ch.K, ch.tiles, false, s));
+        HIPCHK(launch_adj(a, ch.P, ch.K, ch.tiles, true, s));
+    }
+    HIPCHK(hipEventRecord(p->ev_adj[1], s));
+    p->adj_recorded = true;
+    return PH_OK;
 }
 
 ph_status ph_validate(ph_plan *p, const ph_problem *pb, void *stream_v)
@@ -551,12 +742,18 @@ ph_status ph_validate(ph_plan *p, const ph_problem *pb, void *stream_v)
 ph_status ph_plan_stage_ms(ph_plan *p, float ms[4])
 {
     if (!p || !ms) return fail(PH_ERR_INVALID, "NULL argument");
-    if (!p->stages_recorded) return fail(PH_ERR_STATE, "no forward call recorded");
+    if (!p->stages_recorded && !p->adj_recorded) return fail(PH_ERR_STATE, "no forward or backward call recorded");
+    for (int i = 0; i < 4; ++i) ms[i] = 0.0f;
+    if (p->stages_recorded) {
     HIPCHK(hipEventSynchronize(p->ev[3]));
     HIPCHK(hipEventElapsedTime(&ms[0], p->ev[0], p->ev[1]));
     HIPCHK(hipEventElapsedTime(&ms[1], p->ev[1], p->ev[2]));
     HIPCHK(hipEventElapsedTime(&ms[2], p->ev[2], p->ev[3]));
-    ms[3] = 0.0f;
+    }
+    if (p->adj_recorded) {
+        HIPCHK(hipEventSynchronize(p->ev_adj[1]));
+        HIPCHK(hipEventElapsedTime(&ms[3], p->ev_adj[0], p->ev_adj[1]));
+    }
     return PH_OK;
 }
 

@@ -1,0 +1,138 @@
+// Device helpers shared by the HIP translation units of libpairhmm.
+// Internal; every function is inline.  Each translation unit that includes
+// this header defines its own __constant__ Phred table `c_prob` first.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ph_internal.h"
+
+namespace ph {
+
+// ---------------------------------------------------------------------------
+// lane shifts inside groups of P lanes: lane t receives lane t-1's value,
+// the first lane of each group receives 0.
+// ---------------------------------------------------------------------------
+template <int P>
+__device__ __forceinline__ uint32_t shift_up_zero(uint32_t v)
+{
+    int x = (int)v;
+    if constexpr (P == 16) {
+        x = __builtin_amdgcn_mov_dpp(x, 0x111 /* row_shr:1 */, 0xf, 0xf, true);
+    } else if constexpr (P == 64) {
+        x = __builtin_amdgcn_mov_dpp(x, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
+    } else {
+        static_assert(P == 32, "lane groups of 16, 32 or 64");
+        // lanes 16 and 48 take lane 15 / 47 from the previous 16-lane row,
+        // the rest shift inside their row; lanes 0 and 32 keep 0.
+        int t = __builtin_amdgcn_update_dpp(0, x, 0x142 /* row_bcast:15 */, 0xa, 0x1, false);
+        x = __builtin_amdgcn_update_dpp(t, x, 0x111 /* row_shr:1 */, 0xf, 0xf, false);
+    }
+    return (uint32_t)x;
+}
+
+template <int P>
+__device__ __forceinline__ float shift_up(float v)
+{
+    return __builtin_bit_cast(float, shift_up_zero<P>(__builtin_bit_cast(uint32_t, v)));
+}
+
+template <int P>
+__device__ __forceinline__ double shift_up(double v)
+{
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    uint32_t lo = shift_up_zero<P>((uint32_t)u);
+    uint32_t hi = shift_up_zero<P>((uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <typename T>
+struct Range;
+template <>
+struct Range<float> {
+    static constexpr int kExp = 120;
+};
+template <>
+struct Range<double> {
+    static constexpr int kExp = 1020;
+};
+
+
+// lane shifts inside groups of P lanes the other way: lane t receives lane
+// t+1's value, the last lane of each group receives 0.
+template <int P>
+__device__ __forceinline__ uint32_t shift_down_zero(uint32_t v)
+{
+    int x = (int)v;
+    if constexpr (P == 16) {
+        x = __builtin_amdgcn_mov_dpp(x, 0x101 /* row_shl:1 */, 0xf, 0xf, true);
+    } else {
+        static_assert(P == 32 || P == 64, "lane groups of 16, 32 or 64");
+        x = __builtin_amdgcn_mov_dpp(x, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
+        if constexpr (P == 32) {
+            // lane 31 took lane 32's value across the group boundary
+            if ((threadIdx.x & 31) == 31) x = 0;
+        }
+    }
+    return (uint32_t)x;
+}
+
+template <int P>
+__device__ __forceinline__ float shift_down(float v)
+{
+    return __builtin_bit_cast(float, shift_down_zero<P>(__builtin_bit_cast(uint32_t, v)));
+}
+
+template <int P>
+__device__ __forceinline__ double shift_down(double v)
+{
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    uint32_t lo = shift_down_zero<P>((uint32_t)u);
+    uint32_t hi = shift_down_zero<P>((uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Parameters of one read row in linear space.  Phred mode decodes the
+// quality bytes through the FP64 table; explicit mode reads the row's
+// exponentiated parameters, written once per call by k_prep_params.
+struct RowPar {
+    double a, b, d, e, z, lm, lx;
+};
+
+__device__ __forceinline__ RowPar load_row(const DevProblem &pb, const double *lin, int64_t pos,
+                                          const double *c_prob)
+{
+    RowPar r;
+    if (lin) {
+        const double *p = lin + pos * 8;
+        r.a = p[0];
+        r.b = p[1];
+        r.d = p[2];
+        r.e = p[3];
+        r.z = p[4];
+        r.lm = p[5];
+        r.lx = p[6];
+    } else {
+        const double Q = c_prob[pb.bq[pos]];
+        r.d = c_prob[pb.iq[pos]];
+        r.z = c_prob[pb.dq[pos]];
+        r.e = c_prob[pb.gq[pos]];
+        r.a = 1.0 - r.d - r.z;
+        r.b = 1.0 - r.e;
+        r.lm = 1.0 - Q;
+        r.lx = Q / 3.0;
+    }
+    return r;
+}
+
+__device__ __forceinline__ double load_beta(const DevProblem &pb, const double *lin, int64_t pos,
+                                           const double *c_prob)
+{
+    if (lin) return lin[pos * 8 + 1];
+    return 1.0 - c_prob[pb.gq[pos]];
+}
+
+__device__ __forceinline__ uint32_t clamp_code(uint32_t c) { return c > 4u ? 4u : c; }
+
+}  // namespace ph

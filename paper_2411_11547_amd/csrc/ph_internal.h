@@ -86,6 +86,35 @@ struct SweepArgs {
     int32_t plain_count;         // plain: number of records (tiles of 1 pair)
 };
 
+// Adjoint: one record per pair, grouped by (P, K) and tiled G = 64/P pairs
+// at a time; every group of a tile uses the tile's step count S.
+constexpr int kAdjC = 4;  // forward steps per column checkpoint block
+
+struct AdjRec {
+    int32_t read, hap, out, n;
+    int64_t ws_off;  // floats into the workspace of the record's chunk
+    int32_t S, pad;
+};
+
+struct AdjArgs {
+    DevProblem pb;
+    const double *lin_params;
+    const AdjRec *recs;   // records of one chunk of one configuration
+    int32_t nrec;
+    int32_t hs_bytes;     // LDS bytes per group for the staged haplotype
+    float *ws;            // checkpoints of the chunk
+    double *Ls;           // per record: scaled FP32 row-m sum
+    const double *grad_in;  // per output pair
+    float *grad_out;        // per read base x 7
+    double threshold;
+};
+
+hipError_t upload_luts_adjoint();
+bool adj_supported(int P, int K);
+int adj_e_bytes(int P, int K);
+hipError_t launch_adj(const AdjArgs &a, int P, int K, int tiles, bool backward, hipStream_t s);
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
+
 // Launchers (ph_kernels.hip).  All enqueue on `s` and return the HIP status.
 hipError_t upload_luts();
 hipError_t launch_bin_count(const BinArgs &a, hipStream_t s);

@@ -37,6 +37,7 @@
 #include <stdint.h>
 
 #include "ph_internal.h"
+#include "ph_device.h"
 
 namespace ph {
 
@@ -48,54 +49,6 @@ hipError_t upload_luts()
     for (int q = 0; q < 256; ++q) t[q] = pow(10.0, -(double)q / 10.0);
     return hipMemcpyToSymbol(HIP_SYMBOL(c_prob), t, sizeof(t));
 }
-
-// ---------------------------------------------------------------------------
-// lane shifts inside groups of P lanes: lane t receives lane t-1's value,
-// the first lane of each group receives 0.
-// ---------------------------------------------------------------------------
-template <int P>
-__device__ __forceinline__ uint32_t shift_up_zero(uint32_t v)
-{
-    int x = (int)v;
-    if constexpr (P == 16) {
-        x = __builtin_amdgcn_mov_dpp(x, 0x111 /* row_shr:1 */, 0xf, 0xf, true);
-    } else if constexpr (P == 64) {
-        x = __builtin_amdgcn_mov_dpp(x, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
-    } else {
-        static_assert(P == 32, "lane groups of 16, 32 or 64");
-        // lanes 16 and 48 take lane 15 / 47 from the previous 16-lane row,
-        // the rest shift inside their row; lanes 0 and 32 keep 0.
-        int t = __builtin_amdgcn_update_dpp(0, x, 0x142 /* row_bcast:15 */, 0xa, 0x1, false);
-        x = __builtin_amdgcn_update_dpp(t, x, 0x111 /* row_shr:1 */, 0xf, 0xf, false);
-    }
-    return (uint32_t)x;
-}
-
-template <int P>
-__device__ __forceinline__ float shift_up(float v)
-{
-    return __builtin_bit_cast(float, shift_up_zero<P>(__builtin_bit_cast(uint32_t, v)));
-}
-
-template <int P>
-__device__ __forceinline__ double shift_up(double v)
-{
-    uint64_t u = __builtin_bit_cast(uint64_t, v);
-    uint32_t lo = shift_up_zero<P>((uint32_t)u);
-    uint32_t hi = shift_up_zero<P>((uint32_t)(u >> 32));
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-template <typename T>
-struct Range;
-template <>
-struct Range<float> {
-    static constexpr int kExp = 120;
-};
-template <>
-struct Range<double> {
-    static constexpr int kExp = 1020;
-};
 
 // Per-lane LDS layout for one configuration: E[code][plane][lane] of 8-byte
 // entries (two FP32 rows or one FP64 row per plane), then the haplotype
@@ -113,46 +66,6 @@ struct Cfg {
     static constexpr int E_BYTES = kCodes * CODE_BYTES;
     static constexpr int LDS_BYTES = E_BYTES + G * kRingAlloc;
 };
-
-// Parameters of one read row in linear space.  Phred mode decodes the
-// quality bytes through the FP64 table; explicit mode reads the row's
-// exponentiated parameters, written once per call by k_prep_params.
-struct RowPar {
-    double a, b, d, e, z, lm, lx;
-};
-
-__device__ __forceinline__ RowPar load_row(const DevProblem &pb, const double *lin, int64_t pos)
-{
-    RowPar r;
-    if (lin) {
-        const double *p = lin + pos * 8;
-        r.a = p[0];
-        r.b = p[1];
-        r.d = p[2];
-        r.e = p[3];
-        r.z = p[4];
-        r.lm = p[5];
-        r.lx = p[6];
-    } else {
-        const double Q = c_prob[pb.bq[pos]];
-        r.d = c_prob[pb.iq[pos]];
-        r.z = c_prob[pb.dq[pos]];
-        r.e = c_prob[pb.gq[pos]];
-        r.a = 1.0 - r.d - r.z;
-        r.b = 1.0 - r.e;
-        r.lm = 1.0 - Q;
-        r.lx = Q / 3.0;
-    }
-    return r;
-}
-
-__device__ __forceinline__ double load_beta(const DevProblem &pb, const double *lin, int64_t pos)
-{
-    if (lin) return lin[pos * 8 + 1];
-    return 1.0 - c_prob[pb.gq[pos]];
-}
-
-__device__ __forceinline__ uint32_t clamp_code(uint32_t c) { return c > 4u ? 4u : c; }
 
 template <typename T, int P, int K>
 __device__ __forceinline__ void load_lam(T *lam, const char *ebase)
@@ -280,8 +193,8 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     for (int r = 0; r < K; ++r) {
         const int i = t * K + r;  // 0-based read row
         const int ic = min(i, mload - 1);
-        const RowPar p = load_row(pb, lin, ro + ic);
-        const double bn = load_beta(pb, lin, ro + min(i + 1, mload - 1));
+        const RowPar p = load_row(pb, lin, ro + ic, c_prob);
+        const double bn = load_beta(pb, lin, ro + min(i + 1, mload - 1), c_prob);
         const bool real = i < m;
         *slot(0, r) = real ? (T)p.a : (T)0;
         *slot(1, r) = real ? (T)p.b : (T)0;
@@ -300,13 +213,13 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     }
     // D(0, j) = 1/n scaled into range, pre-multiplied by beta_1; lane 0 only
     T edge = 0;
-    if (t == 0 && m > 0) edge = (T)(ldexp(load_beta(pb, lin, ro), Range<T>::kExp) / (double)n);
+    if (t == 0 && m > 0) edge = (T)(ldexp(load_beta(pb, lin, ro, c_prob), Range<T>::kExp) / (double)n);
     // E[c][row] = lam of the row against haplotype code c (N matches all, PAD = 0)
 #pragma unroll 1
     for (int r = 0; r < C::KP; ++r) {
         const int i = t * K + r;
         const int ic = min(i, mload - 1);
-        const RowPar p = load_row(pb, lin, ro + ic);
+        const RowPar p = load_row(pb, lin, ro + ic, c_prob);
         const bool real = (r < K) && (i < m);
         const uint32_t code = clamp_code(pb.read_bases[ro + ic]);
         const T lm = real ? (T)p.lm : (T)0, lx = real ? (T)p.lx : (T)0;

@@ -1,0 +1,153 @@
+"""GPU parity of the adjoint sweep: gradients of sum_p u_p log10 L_p with
+respect to the log10 parameters of every read base, against the FP64 oracle's
+forward-backward and against FP64 central finite differences.
+
+Tolerance: |g - g_ref| <= 1e-3 |g_ref| + 1e-6 elementwise."""
+import numpy as np
+import pytest
+
+from gpu_util import binding, oracle, say, wl
+
+pytestmark = pytest.mark.gpu
+RTOL, ATOL = 1e-3, 1e-6
+
+
+def oracle_grad(prob, u, log10_params=None):
+    """Per read base, sum over the read's pairs of u_p * g_p (oracle)."""
+    lf, g7, off, _ = oracle.backward(prob, log10_params=log10_params)
+    r_idx, _ = prob.pair_index()
+    out = np.zeros((int(prob.read_offset[-1]), 7))
+    for k in range(prob.num_pairs):
+        a = prob.read_offset[r_idx[k]]
+        out[a:a + (off[k + 1] - off[k])] += u[k] * g7[off[k]:off[k + 1]]
+    return out, lf
+
+
+def gpu_grad(prob, u, log10_params=None, **kw):
+    import torch
+    dev = binding.DeviceProblem(prob)
+    plan = binding.Plan(prob, **kw)
+    lp = None if log10_params is None else torch.from_numpy(np.ascontiguousarray(log10_params, np.float32)).cuda()
+    g = plan.backward(dev, torch.from_numpy(np.ascontiguousarray(u, np.float64)).cuda(), log10_params=lp)
+    torch.cuda.synchronize()
+    ms = plan.stage_ms()
+    res = g.cpu().numpy().astype(np.float64)
+    plan.close()
+    return res, ms
+
+
+def compare(got, ref, what):
+    err = np.abs(got - ref)
+    bad = err > RTOL * np.abs(ref) + ATOL
+    rel = float(np.max(err / (np.abs(ref) + ATOL)))
+    say(f"  {what}: {got.shape[0]} rows, max rel err {rel:.2e}, violations {int(bad.sum())}")
+    assert np.all(np.isfinite(got))
+    assert not bad.any(), np.argwhere(bad)[:5]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    yield
+
+
+def test_adjoint_config0_phred():
+    say("adjoint config0, Phred parameters, u = 1")
+    prob = wl.config0()
+    u = np.ones(prob.num_pairs)
+    ref, _ = oracle_grad(prob, u)
+    got, ms = gpu_grad(prob, u)
+    compare(got, ref, "config0")
+
+
+def test_adjoint_shared_reads_weighted():
+    """Reads shared by 8 haplotypes: per-base gradients sum u_p-weighted pair
+    gradients (config1 shape, 3 regions)."""
+    say("adjoint, shared reads, random upstream gradient")
+    prob = wl.config1(regions=3)
+    u = np.random.default_rng(1).normal(size=prob.num_pairs)
+    ref, _ = oracle_grad(prob, u)
+    got, _ = gpu_grad(prob, u)
+    compare(got, ref, "config1x3")
+
+
+def test_adjoint_ragged_lengths():
+    say("adjoint, read lengths across every configuration")
+    rng = np.random.default_rng(2)
+    reads, haps = [], []
+    ref_seq = rng.choice(list("ACGT"), size=700)
+    for m in [1, 2, 5, 31, 32, 63, 64, 95, 96, 127, 128, 158, 159, 160, 191, 192, 250, 255, 256, 300, 318, 319]:
+        s0 = int(rng.integers(0, 700 - m))
+        r = ref_seq[s0:s0 + m].copy()
+        err = rng.random(m) < 0.02
+        r[err] = rng.choice(list("ACGTN"), size=int(err.sum()))
+        reads.append("".join(r))
+    for n in [1, 3, 64, 333, 700]:
+        haps.append("".join(ref_seq[:n]))
+    prob = wl.from_strings([(reads, haps)])
+    prob.base_qual[:] = rng.integers(8, 41, size=len(prob.base_qual))
+    prob.ins_qual[:] = rng.integers(25, 46, size=len(prob.ins_qual))
+    prob.del_qual[:] = rng.integers(25, 46, size=len(prob.del_qual))
+    prob.gcp_qual[:] = rng.integers(5, 20, size=len(prob.gcp_qual))
+    u = np.ones(prob.num_pairs)
+    lf = oracle.forward(prob)
+    keep = lf > -60  # pairs the FP32 sweep handles
+    u[~keep] = 0.0
+    ref, _ = oracle_grad(prob, u)
+    got, _ = gpu_grad(prob, u)
+    # rows whose only pairs were dropped get NaN on the GPU only if u != 0; u = 0 rows stay finite
+    compare(got, ref, "ragged")
+
+
+def test_adjoint_explicit_params():
+    say("adjoint, explicit log10 parameters off the Phred manifold")
+    prob = wl.config4(pairs=40)
+    rng = np.random.default_rng(3)
+    par = oracle.params_from_phred(prob.base_qual, prob.ins_qual, prob.del_qual, prob.gcp_qual)
+    par *= 10 ** rng.uniform(-0.1, 0.1, par.shape)  # stays inside the FP32 sweep's range
+    lg = np.log10(par).astype(np.float32)
+    u = rng.uniform(0.5, 2.0, prob.num_pairs)
+    assert np.all(oracle.forward(prob, log10_params=lg) > -60)
+    ref, _ = oracle_grad(prob, u, log10_params=lg)
+    got, _ = gpu_grad(prob, u, log10_params=lg)
+    compare(got, ref, "explicit")
+
+
+def test_adjoint_config4_full_vs_oracle():
+    say("adjoint, config4 full size (10,000 pairs)")
+    prob = wl.config4()
+    u = np.ones(prob.num_pairs)
+    ref, _ = oracle_grad(prob, u)
+    got, ms = gpu_grad(prob, u)
+    say(f"  adjoint stage {ms[3]:.3f} ms, {prob.total_cells / (ms[3] * 1e-3) / 1e9:.1f} GCUPS")
+    compare(got, ref, "config4")
+
+
+def test_adjoint_vs_central_fd_32_pairs():
+    """FP64 central differences of the oracle forward in log10-parameter space
+    (h = 1e-5) on 32 pairs sampled with default_rng(4), 6 rows each."""
+    say("adjoint vs FP64 central FD, 32 sampled pairs")
+    full = wl.config4()
+    idx = np.sort(np.random.default_rng(4).choice(full.num_pairs, 32, replace=False))
+    prob = full.select_pairs(idx)
+    lg = np.log10(oracle.params_from_phred(prob.base_qual, prob.ins_qual, prob.del_qual, prob.gcp_qual))
+    lg32 = lg.astype(np.float32)
+    got, _ = gpu_grad(prob, np.ones(prob.num_pairs), log10_params=lg32)
+    lin = 10.0 ** lg32.astype(np.float64)
+    rng = np.random.default_rng(5)
+    h = 1e-5
+    errs = []
+    for k in range(prob.num_pairs):
+        a, b = prob.read_offset[k], prob.read_offset[k + 1]
+        read, hap = prob.read_bases[a:b], prob.hap(k)
+        p0 = lin[a:b]
+        for row in rng.choice(b - a, 6, replace=False):
+            for c in range(7):
+                up = p0.copy(); up[row, c] *= 10 ** h
+                dn = p0.copy(); dn[row, c] *= 10 ** -h
+                fd = (oracle.forward_pair(read, hap, up) - oracle.forward_pair(read, hap, dn)) / (2 * h)
+                g = got[a + row, c]
+                errs.append(abs(g - fd) / (abs(fd) + 1e-6))
+                assert abs(g - fd) <= 1e-3 * abs(fd) + 2e-6, (k, row, c, g, fd)
+    say(f"  {len(errs)} FD checks, max rel err {max(errs):.2e}")
