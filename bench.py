@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune-table", default=None)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--launch", choices=["bins", "single"], default="bins",
+                    help="FP32 sweep as one launch per length bin or one persistent launch")
+    ap.add_argument("--no-ab", action="store_true", help="skip timing the other launch mode")
     ap.add_argument("--adjoint-steps", type=int, default=5)
     args = ap.parse_args()
 
@@ -134,7 +137,7 @@ def main():
     log(f"{prob.name}: {prob.num_pairs} pairs, {cells:.3e} cells")
     dev = binding.DeviceProblem(prob)
 
-    plan = binding.Plan(prob, tune_table=args.tune_table)
+    plan = binding.Plan(prob, tune_table=args.tune_table, single_launch=args.launch == "single")
     sec, stages = time_forward(plan, dev, args.steps, args.warmup)
     rescued = plan.rescued()
     gcups = cells / sec / 1e9
@@ -142,6 +145,16 @@ def main():
     log(f"binned: {sec * 1e3:.2f} ms/step, {gcups:.1f} GCUPS, stages(ms) bin={st_mean[0]:.3f} "
         f"fp32={st_mean[1]:.3f} fp64={st_mean[2]:.3f}, rescued {rescued}")
     plan.close()
+
+    other = None
+    if not args.no_ab:
+        mode = "bins" if args.launch == "single" else "single"
+        oplan = binding.Plan(prob, tune_table=args.tune_table, single_launch=mode == "single")
+        osec, ost = time_forward(oplan, dev, max(2, args.steps // 2), 1)
+        other = {"launch": mode, "gcups": round(cells / osec / 1e9, 2),
+                 "fp32_sweep_ms": round(float(ost.mean(axis=0)[1]), 4)}
+        log(f"{mode}: {osec * 1e3:.2f} ms/step, {cells / osec / 1e9:.1f} GCUPS")
+        oplan.close()
 
     plain = None
     if not args.no_plain:
@@ -170,10 +183,12 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32 (f64 rescue)", "data": "synthetic",
            "config": {"workload": prob.name, "pairs": prob.num_pairs, "cells": cells,
-                      "read_len": "50-250", "hap_len": "100-2000", "graph": True},
+                      "read_len": "50-250", "hap_len": "100-2000", "graph": True,
+                      "fp32_launch": args.launch},
            "plain_gcups": None if plain is None else round(plain, 2),
            "binned_vs_plain": None if plain is None else round(gcups / plain, 3),
            "rescued_pairs": int(rescued),
+           "launch": args.launch, "other_launch": other,
            "stage_ms": {"binning": round(float(st_mean[0]), 4), "fp32_sweep": round(float(st_mean[1]), 4),
                         "fp64_rescue": round(float(st_mean[2]), 4)},
            "adjoint_gcups": None if adj is None else adj["gcups"],

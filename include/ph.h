@@ -100,9 +100,13 @@ typedef struct {
     int plain;             /* 1: one FP32 kernel sized for the longest read, pairs
                               in output order, no binning, no rescue (baseline) */
     int force_p;           /* 0 = tuned; else lanes per pair (16, 32 or 64) for every bin */
-    int keep_checkpoints;  /* 1: forward stores what ph_backward_batch needs */
+    int keep_checkpoints;  /* 1: build the adjoint's tables and workspace at plan
+                              time (else on the first ph_backward_batch) */
     const char *tune_table_path; /* NULL = built-in table; else a text file of
                                     "max_read_len lanes rows_per_lane" lines */
+    int single_launch;     /* 1: one persistent FP32 launch drains every bin when all
+                              non-empty bins use 16 lanes and 3..16 rows per lane
+                              (reads up to 255); otherwise one launch per bin */
 } ph_plan_opts;
 
 typedef struct ph_plan ph_plan; /* opaque: owns scratch, queues, checkpoints, graph */
@@ -134,10 +138,14 @@ ph_status ph_forward_batch(ph_plan *plan, const ph_problem *problem,
 
 /* Adjoint pass: grad_params[read_offset[num_reads]][7] (device, float)
  * receives d(sum_p u_p log10 L_p)/d log10 theta for the seven parameters of
- * every read base, u = grad_log10L[P] (device, double).  Requires a preceding
- * ph_forward_batch on the same plan, problem and parameters, with
- * keep_checkpoints set (PH_ERR_STATE otherwise).  The gradient buffer is
- * overwritten, not accumulated into. */
+ * every read base, u = grad_log10L[P] (device, double).  The call runs its
+ * own checkpointed FP32 forward (row checkpoints at every lane boundary,
+ * lane-state checkpoints every 4 columns) and then the reverse sweep, so it
+ * needs no preceding forward call.  The gradient buffer is overwritten.
+ * Reads longer than 319 bases give PH_ERR_UNSUPPORTED.  Pairs whose scaled
+ * FP32 sum leaves the FP32 range get NaN gradients unless their upstream
+ * gradient is 0.  Sums over pairs sharing a read use float atomics, so the
+ * last bits of a gradient may depend on completion order. */
 ph_status ph_backward_batch(ph_plan *plan, const ph_problem *problem,
                             const float *log10_params, const double *grad_log10L,
                             float *grad_params, void *stream);

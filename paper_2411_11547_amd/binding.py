@@ -15,6 +15,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpairhmm.so")
+# bin table measured by tune.py on MI355X; "builtin" selects the library's own
+TUNED_TABLE = os.path.join(HERE, "tune_gfx950.txt")
 
 PH_OK = 0
 STATUS_NAMES = {0: "PH_OK", -1: "PH_ERR_INVALID", -2: "PH_ERR_UNSUPPORTED", -3: "PH_ERR_NOMEM",
@@ -44,7 +46,8 @@ class PhProblem(ctypes.Structure):
 class PhPlanOpts(ctypes.Structure):
     _fields_ = [("rescue_threshold", ctypes.c_double), ("use_graph", ctypes.c_int),
                 ("plain", ctypes.c_int), ("force_p", ctypes.c_int),
-                ("keep_checkpoints", ctypes.c_int), ("tune_table_path", ctypes.c_char_p)]
+                ("keep_checkpoints", ctypes.c_int), ("tune_table_path", ctypes.c_char_p),
+                ("single_launch", ctypes.c_int)]
 
 
 class PHError(RuntimeError):
@@ -199,7 +202,7 @@ class Plan:
     """A plan for one problem shape, with device output buffers."""
 
     def __init__(self, problem, rescue_threshold=None, use_graph=True, plain=False, force_p=0,
-                 keep_checkpoints=False, tune_table=None):
+                 keep_checkpoints=False, tune_table=None, single_launch=False):
         opts = ph_plan_opts_default()
         if rescue_threshold is not None:
             opts.rescue_threshold = float(rescue_threshold)
@@ -207,6 +210,11 @@ class Plan:
         opts.plain = int(bool(plain))
         opts.force_p = int(force_p)
         opts.keep_checkpoints = int(bool(keep_checkpoints))
+        opts.single_launch = int(bool(single_launch))
+        if tune_table is None and not force_p and os.path.exists(TUNED_TABLE):
+            tune_table = TUNED_TABLE
+        if tune_table == "builtin":
+            tune_table = None
         self._tune = tune_table.encode() if tune_table else None
         opts.tune_table_path = self._tune
         shape, self._keep = shape_of(problem)

@@ -84,6 +84,15 @@ std::vector<TuneEntry> default_table(int force_p)
     return t;
 }
 
+// Table for the single-launch sweep: reads shorter than 48 share the K = 3 bin.
+std::vector<TuneEntry> single_table()
+{
+    std::vector<TuneEntry> t;
+    for (int K = 3; K <= 16; ++K) t.push_back({16 * K - 1, 16, K});
+    for (int K = 5; K <= 16; ++K) t.push_back({64 * K - 1, 64, K});
+    return t;
+}
+
 ph_status read_table(const char *path, std::vector<TuneEntry> &t)
 {
     std::ifstream f(path);
@@ -123,6 +132,8 @@ struct ph_plan {
     int64_t class_pairs[kRescueClasses] = {0, 0, 0, 0};
     int rescue_grid[kRescueClasses] = {0, 0, 0, 0};
     int plain_K = 0, plain_grid = 0;
+    bool single = false;   // one persistent FP32 launch over all bins
+    int single_grid = 0;
 
     int64_t *d_out_offset = nullptr;
     int16_t *d_m2bin = nullptr;
@@ -399,6 +410,8 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     if (opts.tune_table_path) {
         ph_status st = read_table(opts.tune_table_path, p->table);
         if (st != PH_OK) return st;
+    } else if (opts.single_launch && !opts.force_p) {
+        p->table = single_table();
     } else {
         p->table = default_table(opts.force_p);
     }
@@ -435,6 +448,20 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
         const int64_t tiles = (p->bin_pairs[b] + binG[b] - 1) / binG[b];
         const int64_t cap = (int64_t)p->cus * fwd32_blocks_per_cu(e.P, e.K);
         p->bin_grid[b] = (int)std::min<int64_t>(tiles, cap);
+    }
+    if (opts.single_launch && !opts.plain) {
+        bool ok = true;
+        int64_t tiles = 0;
+        for (int b = 0; b < nbins; ++b) {
+            if (!p->bin_pairs[b]) continue;
+            const TuneEntry &e = p->table[nbins - 1 - b];
+            ok = ok && single_supported(e.P, e.K);
+            tiles += (p->bin_pairs[b] + binG[b] - 1) / binG[b];
+        }
+        if (ok && tiles > 0) {
+            p->single = true;
+            p->single_grid = (int)std::min<int64_t>(tiles, (int64_t)p->cus * fwd32_single_blocks_per_cu());
+        }
     }
     for (int c = 0; c < kRescueClasses; ++c)
         if (p->class_pairs[c])
@@ -568,6 +595,8 @@ ph_status enqueue_stage(ph_plan *p, int stage, const ph_problem *pb, const float
     } else if (stage == 1) {
         if (p->opts.plain) {
             HIPCHK(launch_plain32(sa, p->plain_K, p->plain_grid, s));
+        } else if (p->single) {
+            HIPCHK(launch_fwd32_single(sa, p->single_grid, s));
         } else {
             // bins longest first, round-robin over side streams forked from s
             HIPCHK(hipEventRecord(p->fork, s));

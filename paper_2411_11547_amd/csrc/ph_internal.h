@@ -123,6 +123,9 @@ hipError_t launch_bin_scatter(const BinArgs &a, hipStream_t s);
 hipError_t launch_plain_records(const BinArgs &a, hipStream_t s);
 hipError_t launch_fwd32(const SweepArgs &a, int P, int K, int bin, int grid, hipStream_t s);
 hipError_t launch_plain32(const SweepArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_fwd32_single(const SweepArgs &a, int grid, hipStream_t s);
+int fwd32_single_blocks_per_cu();
+bool single_supported(int P, int K);
 hipError_t launch_fwd64(const SweepArgs &a, int cls, int grid, hipStream_t s);
 hipError_t launch_prep_params(const float *lg, int64_t npos, double *lin, hipStream_t s);
 hipError_t launch_validate(const DevProblem &pb, int64_t nread_bases, int64_t nhap_bases,

@@ -319,6 +319,39 @@ __global__ __launch_bounds__(64) void k_fwd32(SweepArgs A, int bin)
     }
 }
 
+// One persistent FP32 launch over every length bin of 16-lane groups with
+// K = 3..16 rows per lane (reads up to 255 bases): the wave takes the next
+// tile from one cursor and dispatches on the tile's bin.  Bins are laid out
+// longest first, so waves drain the long tiles first.  (Configurations with
+// other lane counts run as one launch per bin.)
+#define PH_SINGLE_CONFIGS(X) \
+    X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_fwd32_single(SweepArgs A)
+{
+    __shared__ __attribute__((aligned(16))) char lds[Cfg<float, 16, 16>::LDS_BYTES];
+    Book *bk = A.book;
+    const int ntiles = bk->bin_tile_begin[A.num_bins];
+    int tile = next_tile(&bk->tile_counter);
+    while (tile < ntiles) {
+        int b = 0;
+        while (tile >= bk->bin_tile_begin[b + 1]) ++b;
+        constexpr int G = 4;
+        const int first = bk->bin_rec_begin[b] + (tile - bk->bin_tile_begin[b]) * G;
+        const int nvalid = min(G, bk->bin_rec_begin[b + 1] - first);
+        switch (A.bins[b].K) {
+#define PH_SC(k) \
+    case k: sweep_tile<float, 16, k>(A, nullptr, first, nvalid, lds); break;
+            PH_SINGLE_CONFIGS(PH_SC)
+#undef PH_SC
+        default: break;
+        }
+        tile = next_tile(&bk->tile_counter);
+    }
+}
+
+bool single_supported(int P, int K) { return P == 16 && K >= 3 && K <= 16; }
+
 // Plain FP32 sweep: one pair per wave, pairs in output order, one (64, K).
 template <int K>
 __global__ __launch_bounds__(64) void k_plain32(SweepArgs A)
@@ -507,6 +540,8 @@ __global__ __launch_bounds__(256) void k_validate(const uint8_t *rb, int64_t nr,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+static int occupancy(const void *fn);
+
 static int grid_for(int64_t items, int per_block, int cap)
 {
     int64_t g = (items + per_block - 1) / per_block;
@@ -556,6 +591,16 @@ hipError_t launch_fwd32(const SweepArgs &a_in, int P, int K, int bin, int grid, 
 #undef PH_L32
     return hipErrorInvalidValue;
 }
+
+hipError_t launch_fwd32_single(const SweepArgs &a_in, int grid, hipStream_t s)
+{
+    SweepArgs a = a_in;
+    a.mode = kModeBinned;
+    hipLaunchKernelGGL(k_fwd32_single, dim3(grid), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+int fwd32_single_blocks_per_cu() { return occupancy((const void *)k_fwd32_single); }
 
 hipError_t launch_plain32(const SweepArgs &a_in, int K, int grid, hipStream_t s)
 {

@@ -173,6 +173,17 @@ def test_config2_reduced_all_pairs():
     check_against_oracle(prob, got, st)
 
 
+def test_single_launch_mixed():
+    """One persistent FP32 launch over every bin (reads <= 255)."""
+    say("single persistent launch, config2 subset")
+    prob = wl.config2(regions=24)
+    got, st = gpu_forward(prob, single_launch=True)
+    check_against_oracle(prob, got, st)
+    short = _ragged(3, [[1, 2, 20, 47, 48, 100, 255]], [[1, 64, 300]])
+    got, st = gpu_forward(short, single_launch=True)
+    check_against_oracle(short, got, st)
+
+
 def test_config1_full_size_sampled():
     """512,000 pairs in the launch configuration the benchmark times; 1,500
     sampled outputs checked one by one against the oracle."""
