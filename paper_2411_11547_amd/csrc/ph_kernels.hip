@@ -42,12 +42,24 @@
 namespace ph {
 
 __constant__ double c_prob[256];  // Phred q -> 10^(-q/10), computed on the host in FP64
+// the same table rounded to FP32, and 1 - p, p / 3 formed in FP64 then rounded
+__constant__ float c_pf[256], c_1mpf[256], c_pd3f[256];
 
 hipError_t upload_luts()
 {
     double t[256];
-    for (int q = 0; q < 256; ++q) t[q] = pow(10.0, -(double)q / 10.0);
-    return hipMemcpyToSymbol(HIP_SYMBOL(c_prob), t, sizeof(t));
+    float f[256], g[256], h[256];
+    for (int q = 0; q < 256; ++q) {
+        t[q] = pow(10.0, -(double)q / 10.0);
+        f[q] = (float)t[q];
+        g[q] = (float)(1.0 - t[q]);
+        h[q] = (float)(t[q] / 3.0);
+    }
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_prob), t, sizeof(t));
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_pf), f, sizeof(f));
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_1mpf), g, sizeof(g));
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_pd3f), h, sizeof(h));
+    return e;
 }
 
 // Per-lane LDS layout for one configuration: E[code][plane][lane] of 8-byte
@@ -64,7 +76,8 @@ struct Cfg {
     static constexpr int KP = NPL * RPP;
     static constexpr int CODE_BYTES = NPL * 512;
     static constexpr int E_BYTES = kCodes * CODE_BYTES;
-    static constexpr int LDS_BYTES = E_BYTES + G * kRingAlloc;
+    static constexpr int RING_BYTES = kRingAlloc * 2;  // u16 E-table offsets
+    static constexpr int LDS_BYTES = E_BYTES + G * RING_BYTES;
 };
 
 template <typename T, int P, int K>
@@ -83,9 +96,11 @@ __device__ __forceinline__ void load_lam(T *lam, const char *ebase)
     }
 }
 
-// Write chunk `chunk` (64 columns) of the group's haplotype into its ring.
+// Write chunk `chunk` (64 columns) of the group's haplotype into its ring,
+// as byte offsets of the code's E table (code * code_bytes).
 template <int P>
-__device__ __forceinline__ void ring_fill(uint8_t *ring, int chunk, const uint8_t *hap, int n, int t)
+__device__ __forceinline__ void ring_fill(uint16_t *ring, int chunk, const uint8_t *hap, int n, int t,
+                                          int code_bytes)
 {
     constexpr int PER = kChunk / P;  // columns per lane
     const int slot = chunk & 3;
@@ -93,9 +108,10 @@ __device__ __forceinline__ void ring_fill(uint8_t *ring, int chunk, const uint8_
     for (int b = 0; b < PER; ++b) {
         int x = t * PER + b;
         int col = chunk * kChunk + x;
-        uint8_t c = col < n ? (uint8_t)clamp_code(hap[col]) : (uint8_t)kPad;
-        ring[slot * kChunk + x] = c;
-        if (slot == 0) ring[kRing + x] = c;
+        const uint32_t c = col < n ? clamp_code(hap[col]) : (uint32_t)kPad;
+        const uint16_t off = (uint16_t)(c * code_bytes);
+        ring[slot * kChunk + x] = off;
+        if (slot == 0) ring[kRing + x] = off;
     }
 }
 
@@ -113,12 +129,13 @@ __device__ __forceinline__ int next_tile(int32_t *cursor)
 
 // One anti-diagonal step of a lane: column j = s - t + 1 of rows tK+1..tK+K.
 // M, I, D hold column j-1 on entry and column j on exit; (Md, Id, Dd) are the
-// values of the row above the lane's first row at column j-1.
+// values of the row above the lane's first row at column j-1, received from
+// lane t-1 at the previous step.  The D shift folds into one v_add_f32_dpp
+// with the row-0 edge value.
 template <typename T, int P, int K>
-__device__ __forceinline__ void cell_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md, T &Id, T &Dd,
-                                          const T *lam, const T (&al)[K], const T (&be)[K],
-                                          const T (&de)[K], const T (&ep)[K], const T (&zt)[K],
-                                          T edge, double &acc)
+__device__ __forceinline__ void cell_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md, T &Id, T &Dd, const T *lam,
+                                          const T (&al)[K], const T (&be)[K], const T (&de)[K],
+                                          const T (&ep)[K], const T (&zt)[K], T edge, T &acc)
 {
     const T Mu = shift_up<P>(M[K - 1]);
     const T Iu = shift_up<P>(I[K - 1]);
@@ -144,7 +161,7 @@ __device__ __forceinline__ void cell_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md
     Md = Mu;
     Id = Iu;
     Dd = Du;
-    acc += (double)I[K - 1];
+    acc += I[K - 1];
 }
 
 // Sweep one tile: up to G = 64/P pairs, one per lane group.  Group g takes
@@ -177,88 +194,152 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     nmax = __builtin_amdgcn_readfirstlane(nmax);
 
     // ---- prologue: parameters of my rows, my slice of the E table ----------
-    // Row parameters are computed one row at a time (a rolled loop keeps the
-    // FP64 decoding out of the sweep's register budget) and parked in the
-    // lane's own E-table entries, then loaded into registers; the E entries
-    // are written afterwards.  Loads use clamped row indices so that they
-    // stay inside the read; padding rows get their absorbing parameters.
+    // Loads use clamped row indices so that they stay inside the read;
+    // padding rows then get their absorbing parameters by select.
     char *E = lds;
     char *mine = E + lane * 8;
-    uint8_t *ring = (uint8_t *)(lds + C::E_BYTES + g * kRingAlloc);
+    uint16_t *ring = (uint16_t *)(lds + C::E_BYTES + g * C::RING_BYTES);
     auto slot = [&](int c, int r) -> T * {
         return (T *)(mine + c * C::CODE_BYTES + (r / C::RPP) * 512 + (r % C::RPP) * (int)sizeof(T));
     };
     const int mload = m > 0 ? m : 1;
-#pragma unroll 1
-    for (int r = 0; r < K; ++r) {
-        const int i = t * K + r;  // 0-based read row
-        const int ic = min(i, mload - 1);
-        const RowPar p = load_row(pb, lin, ro + ic, c_prob);
-        const double bn = load_beta(pb, lin, ro + min(i + 1, mload - 1), c_prob);
-        const bool real = i < m;
-        *slot(0, r) = real ? (T)p.a : (T)0;
-        *slot(1, r) = real ? (T)p.b : (T)0;
-        *slot(2, r) = real ? (T)p.d : (i == m ? (T)1 : (T)0);
-        *slot(3, r) = real ? (T)p.e : (T)1;
-        *slot(4, r) = (real && i + 1 < m) ? (T)(bn * p.z) : (T)0;
-    }
     T al[K], be[K], de[K], ep[K], zt[K];
-#pragma unroll
-    for (int r = 0; r < K; ++r) {
-        al[r] = *slot(0, r);
-        be[r] = *slot(1, r);
-        de[r] = *slot(2, r);
-        ep[r] = *slot(3, r);
-        zt[r] = *slot(4, r);
-    }
-    // D(0, j) = 1/n scaled into range, pre-multiplied by beta_1; lane 0 only
     T edge = 0;
-    if (t == 0 && m > 0) edge = (T)(ldexp(load_beta(pb, lin, ro, c_prob), Range<T>::kExp) / (double)n);
-    // E[c][row] = lam of the row against haplotype code c (N matches all, PAD = 0)
-#pragma unroll 1
-    for (int r = 0; r < C::KP; ++r) {
-        const int i = t * K + r;
-        const int ic = min(i, mload - 1);
-        const RowPar p = load_row(pb, lin, ro + ic, c_prob);
-        const bool real = (r < K) && (i < m);
-        const uint32_t code = clamp_code(pb.read_bases[ro + ic]);
-        const T lm = real ? (T)p.lm : (T)0, lx = real ? (T)p.lx : (T)0;
+    if (sizeof(T) == 4 && !lin) {
+        // FP32 sweep, Phred mode: all of the lane's loads issued at once,
+        // decoded through the FP32 tables (1 - p and p/3 rounded from FP64);
+        // the E table first, then the transition parameters
+        {
+            uint32_t bq[C::KP], code[C::KP];
 #pragma unroll
-        for (int c = 0; c < kCodes; ++c) {
-            const bool match = code == (uint32_t)c || code == 4u || c == 4;
-            *slot(c, r) = c == kPad ? (T)0 : (match ? lm : lx);
+            for (int r = 0; r < C::KP; ++r) {
+                const int64_t pos = ro + min(t * K + r, mload - 1);
+                bq[r] = pb.bq[pos];
+                code[r] = clamp_code(pb.read_bases[pos]);
+            }
+#pragma unroll
+            for (int q = 0; q < C::NPL; ++q) {
+                float lm[C::RPP], lx[C::RPP];
+#pragma unroll
+                for (int rr = 0; rr < C::RPP; ++rr) {
+                    const int r = q * C::RPP + rr;
+                    const bool real = (r < K) && (t * K + r < m);
+                    lm[rr] = real ? c_1mpf[bq[r]] : 0.f;
+                    lx[rr] = real ? c_pd3f[bq[r]] : 0.f;
+                }
+#pragma unroll
+                for (int c = 0; c < kCodes; ++c) {
+                    T v[C::RPP];
+#pragma unroll
+                    for (int rr = 0; rr < C::RPP; ++rr) {
+                        const int r = q * C::RPP + rr;
+                        const bool match = code[r] == (uint32_t)c || code[r] == 4u || c == 4;
+                        v[rr] = c == kPad ? (T)0 : (T)(match ? lm[rr] : lx[rr]);
+                    }
+                    if constexpr (sizeof(T) == 4)
+                        *(float2 *)(mine + c * C::CODE_BYTES + q * 512) = make_float2(v[0], v[1]);
+                    else
+                        *(double *)(mine + c * C::CODE_BYTES + q * 512) = v[0];
+                }
+            }
+        }
+        {
+            uint32_t iq[K], dq[K], gq[K + 1];
+#pragma unroll
+            for (int r = 0; r <= K; ++r) {
+                const int64_t pos = ro + min(t * K + r, mload - 1);
+                gq[r] = pb.gq[pos];
+                if (r < K) {
+                    iq[r] = pb.iq[pos];
+                    dq[r] = pb.dq[pos];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                const int i = t * K + r;
+                const bool real = i < m;
+                const float d = c_pf[iq[r]], z = c_pf[dq[r]];
+                al[r] = real ? (T)(1.0f - d - z) : (T)0;
+                be[r] = real ? (T)c_1mpf[gq[r]] : (T)0;
+                de[r] = real ? (T)d : (i == m ? (T)1 : (T)0);
+                ep[r] = real ? (T)c_pf[gq[r]] : (T)1;
+                zt[r] = (real && i + 1 < m) ? (T)(c_1mpf[gq[r + 1]] * z) : (T)0;
+            }
+            if (t == 0 && m > 0) edge = (T)(ldexp((double)c_1mpf[gq[0]], Range<T>::kExp) / (double)n);
+        }
+    } else {
+        // FP64 sweep or explicit parameters: one row at a time in FP64, the
+        // row parameters parked in the lane's own E entries, then loaded
+#pragma unroll 1
+        for (int r = 0; r < K; ++r) {
+            const int i = t * K + r;
+            const int ic = min(i, mload - 1);
+            const RowPar p = load_row(pb, lin, ro + ic, c_prob);
+            const double bn = load_beta(pb, lin, ro + min(i + 1, mload - 1), c_prob);
+            const bool real = i < m;
+            *slot(0, r) = real ? (T)p.a : (T)0;
+            *slot(1, r) = real ? (T)p.b : (T)0;
+            *slot(2, r) = real ? (T)p.d : (i == m ? (T)1 : (T)0);
+            *slot(3, r) = real ? (T)p.e : (T)1;
+            *slot(4, r) = (real && i + 1 < m) ? (T)(bn * p.z) : (T)0;
+        }
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            al[r] = *slot(0, r);
+            be[r] = *slot(1, r);
+            de[r] = *slot(2, r);
+            ep[r] = *slot(3, r);
+            zt[r] = *slot(4, r);
+        }
+        if (t == 0 && m > 0) edge = (T)(ldexp(load_beta(pb, lin, ro, c_prob), Range<T>::kExp) / (double)n);
+        // E[c][row] = lam of the row against haplotype code c (N matches all, PAD = 0)
+#pragma unroll 1
+        for (int r = 0; r < C::KP; ++r) {
+            const int i = t * K + r;
+            const int ic = min(i, mload - 1);
+            const RowPar p = load_row(pb, lin, ro + ic, c_prob);
+            const bool real = (r < K) && (i < m);
+            const uint32_t code = clamp_code(pb.read_bases[ro + ic]);
+            const T lm = real ? (T)p.lm : (T)0, lx = real ? (T)p.lx : (T)0;
+#pragma unroll
+            for (int c = 0; c < kCodes; ++c) {
+                const bool match = code == (uint32_t)c || code == 4u || c == 4;
+                *slot(c, r) = c == kPad ? (T)0 : (match ? lm : lx);
+            }
         }
     }
     // haplotype ring: PAD everywhere (negative columns read slot 3), then chunks 0 and 1
-    for (int x = t; x < kRingAlloc; x += P) ring[x] = (uint8_t)kPad;
+    for (int x = t; x < kRingAlloc; x += P) ring[x] = (uint16_t)(kPad * C::CODE_BYTES);
     __syncthreads();
-    ring_fill<P>(ring, 0, hap, n, t);
-    ring_fill<P>(ring, 1, hap, n, t);
+    ring_fill<P>(ring, 0, hap, n, t, C::CODE_BYTES);
+    ring_fill<P>(ring, 1, hap, n, t, C::CODE_BYTES);
 
     // ---- sweep ----------------------------------------------------------------
     T M[K], I[K], D[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) M[r] = I[r] = D[r] = 0;
-    T Md = 0, Id = 0, Dd = edge;  // row 0 at column 0
-    double acc = 0.0;
+    T Md = 0, Id = 0, Dd = edge;  // row above the lane's first row, column j-1
+    double acc = 0.0;          // row-m sum; each 64-step chunk is summed in T first
     // steps run in pairs; a step past the last column only meets PAD columns
     // in the last lane and adds exact zeros
     const int total = (nmax + P - 1 + 1) & ~1;
     const char *ebase_lane = E + lane * 8;
 
     for (int s0 = 0; s0 < total; s0 += kChunk) {
-        ring_fill<P>(ring, s0 / kChunk + 2, hap, n, t);
+        ring_fill<P>(ring, s0 / kChunk + 2, hap, n, t, C::CODE_BYTES);
         __syncthreads();
-        const uint8_t *hp = ring + ((s0 - t) & (kRing - 1));
+        const uint16_t *hp = ring + ((s0 - t) & (kRing - 1));
         const int cnt = min(kChunk, total - s0);
         T la[C::KP], lb[C::KP];
-        load_lam<T, P, K>(la, ebase_lane + (int)hp[0] * C::CODE_BYTES);
+        T part = 0;
+        load_lam<T, P, K>(la, ebase_lane + hp[0]);
         for (int u = 0; u < cnt; u += 2) {
-            load_lam<T, P, K>(lb, ebase_lane + (int)hp[u + 1] * C::CODE_BYTES);
-            cell_step<T, P, K>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, edge, acc);
-            load_lam<T, P, K>(la, ebase_lane + (int)hp[u + 2] * C::CODE_BYTES);
-            cell_step<T, P, K>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, edge, acc);
+            load_lam<T, P, K>(lb, ebase_lane + hp[u + 1]);
+            cell_step<T, P, K>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, edge, part);
+            load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
+            cell_step<T, P, K>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, edge, part);
         }
+        acc += (double)part;
         __syncthreads();
     }
 
@@ -303,8 +384,11 @@ bool fwd32_supported(int P, int K)
 // Persistent FP32 sweep over the tiles of one length bin: every wave takes
 // the next tile (one read/haplotype pair per lane group) from the bin's
 // cursor.  Records of a bin are ordered longest haplotype first.
+// waves per SIMD each configuration should reach (register budget 512 / W)
+constexpr int waves_for(int K) { return K <= 6 ? 4 : K <= 10 ? 3 : 2; }
+
 template <int P, int K>
-__global__ __launch_bounds__(64) void k_fwd32(SweepArgs A, int bin)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K)))) void k_fwd32(SweepArgs A, int bin)
 {
     __shared__ __attribute__((aligned(16))) char lds[Cfg<float, P, K>::LDS_BYTES];
     Book *bk = A.book;
