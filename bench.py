@@ -103,6 +103,42 @@ def cpu_baseline(prob, target_cells=2.0e10, seed=0):
                       "FP64 full-matrix forward, gcc -O2"}
 
 
+def precision_report(steps=3):
+    """Precision stress workload (50,000 pairs, 250 bp reads, 1,000-5,000 bp
+    haplotypes at 5-15% divergence, 30% low-quality reads, 2% N): forward
+    GCUPS, rescue fraction and per-pair |d log10 L| against the FP64 oracle,
+    split by the path that produced the result."""
+    import torch
+    import oracle
+    from paper_2411_11547_amd import binding, workloads as wl
+    prob = wl.config3()
+    dev = binding.DeviceProblem(prob)
+    plan = binding.Plan(prob)
+    sec, st = time_forward(plan, dev, steps, 1)
+    out, status = plan.forward(dev)
+    torch.cuda.synchronize()
+    got, status = out.cpu().numpy(), status.cpu().numpy()
+    plan.close()
+    t0 = time.perf_counter()
+    ref, used = oracle.forward(prob, return_threads=True)
+    tor = time.perf_counter() - t0
+    err = np.abs(got - ref)
+    rep = {"workload": prob.name, "pairs": prob.num_pairs, "cells": prob.total_cells,
+           "gcups": round(prob.total_cells / sec / 1e9, 2),
+           "stage_ms": {"fp32_sweep": round(float(st.mean(axis=0)[1]), 3),
+                        "fp64_rescue": round(float(st.mean(axis=0)[2]), 3)},
+           "oracle_s": round(tor, 1), "oracle_threads": int(used),
+           "log10L_range": [round(float(ref.min()), 2), round(float(ref.max()), 2)]}
+    for name, code in (("fp32", 0), ("fp64", 1), ("fp64_floor", 2)):
+        sel = status == code
+        e = err[sel]
+        rep[name] = {"pairs": int(sel.sum()), "fraction": round(float(sel.mean()), 4),
+                     "max_abs_dlog10L": float(e.max()) if e.size and code != 2 else None,
+                     "p99_abs_dlog10L": float(np.percentile(e, 99)) if e.size and code != 2 else None}
+    log(json.dumps(rep))
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +153,10 @@ def main():
     ap.add_argument("--launch", choices=["bins", "single"], default="bins",
                     help="FP32 sweep as one launch per length bin or one persistent launch")
     ap.add_argument("--no-ab", action="store_true", help="skip timing the other launch mode")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a device buffer of this many MiB (counter calibration)")
+    ap.add_argument("--precision", action="store_true",
+                    help="only run the precision-stress report (all pairs against the oracle)")
     ap.add_argument("--adjoint-steps", type=int, default=5)
     args = ap.parse_args()
 
@@ -131,10 +171,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     binding.load()
+    if args.precision:
+        print(json.dumps(precision_report()), flush=True)
+        return
     log(f"generating workload {args.config}")
     prob = workload(args.config)
     cells = prob.total_cells
     log(f"{prob.name}: {prob.num_pairs} pairs, {cells:.3e} cells")
+    read_len = f"{int(prob.read_lengths.min())}-{int(prob.read_lengths.max())}"
+    hap_len = f"{int(prob.hap_lengths.min())}-{int(prob.hap_lengths.max())}"
     dev = binding.DeviceProblem(prob)
 
     plan = binding.Plan(prob, tune_table=args.tune_table, single_launch=args.launch == "single")
@@ -183,7 +228,7 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32 (f64 rescue)", "data": "synthetic",
            "config": {"workload": prob.name, "pairs": prob.num_pairs, "cells": cells,
-                      "read_len": "50-250", "hap_len": "100-2000", "graph": True,
+                      "read_len": read_len, "hap_len": hap_len, "graph": True,
                       "fp32_launch": args.launch},
            "plain_gcups": None if plain is None else round(plain, 2),
            "binned_vs_plain": None if plain is None else round(gcups / plain, 3),
@@ -195,6 +240,12 @@ def main():
            "adjoint": adj,
            "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
+    if args.copy_probe_mib:
+        x = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        torch.cuda.synchronize()
+        y = x.clone()
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written ({float(y[0]):.0f})")
 
 
 if __name__ == "__main__":

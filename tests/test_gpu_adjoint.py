@@ -151,3 +151,26 @@ def test_adjoint_vs_central_fd_32_pairs():
                 errs.append(abs(g - fd) / (abs(fd) + 1e-6))
                 assert abs(g - fd) <= 1e-3 * abs(fd) + 2e-6, (k, row, c, g, fd)
     say(f"  {len(errs)} FD checks, max rel err {max(errs):.2e}")
+
+
+def test_autograd_function_end_to_end():
+    """torch.autograd through PairHMMLogLik: loss = sum_p w_p log10 L_p."""
+    import torch
+    from paper_2411_11547_amd import autograd as ag
+    say("torch.autograd.Function end to end")
+    prob = wl.config4(pairs=64)
+    lg = np.log10(oracle.params_from_phred(prob.base_qual, prob.ins_qual, prob.del_qual, prob.gcp_qual))
+    lg32 = lg.astype(np.float32)
+    dev = binding.DeviceProblem(prob)
+    plan = binding.Plan(prob)
+    x = torch.from_numpy(lg32).cuda().requires_grad_(True)
+    w = torch.from_numpy(np.random.default_rng(9).uniform(0.5, 1.5, prob.num_pairs)).cuda()
+    y = ag.pairhmm_log10_likelihood(x, plan, dev)
+    assert y.dtype == torch.float64 and y.shape == (prob.num_pairs,)
+    (y * w).sum().backward()
+    torch.cuda.synchronize()
+    ref_y = oracle.forward(prob, log10_params=lg32)
+    assert np.max(np.abs(y.detach().cpu().numpy() - ref_y)) <= 1e-3
+    ref_g, _ = oracle_grad(prob, w.cpu().numpy(), log10_params=lg32)
+    compare(x.grad.cpu().numpy().astype(np.float64), ref_g, "autograd")
+    plan.close()
