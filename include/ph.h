@@ -138,14 +138,18 @@ ph_status ph_forward_batch(ph_plan *plan, const ph_problem *problem,
 
 /* Adjoint pass: grad_params[read_offset[num_reads]][7] (device, float)
  * receives d(sum_p u_p log10 L_p)/d log10 theta for the seven parameters of
- * every read base, u = grad_log10L[P] (device, double).  The call runs its
- * own checkpointed FP32 forward (row checkpoints at every lane boundary,
- * lane-state checkpoints every 4 columns) and then the reverse sweep, so it
- * needs no preceding forward call.  The gradient buffer is overwritten.
- * Reads longer than 319 bases give PH_ERR_UNSUPPORTED.  Pairs whose scaled
- * FP32 sum leaves the FP32 range get NaN gradients unless their upstream
- * gradient is 0.  Sums over pairs sharing a read use float atomics, so the
- * last bits of a gradient may depend on completion order. */
+ * every read base, u = grad_log10L[P] (device, double).  The derivative of
+ * Eq. (1)-(4) run backwards; d log10 L / d log10 theta is the posterior
+ * expected number of uses of theta.  The call runs its own checkpointed FP32
+ * forward (row checkpoints at every lane boundary, lane-state checkpoints
+ * every 4 columns) and then the reverse sweep, so it needs no preceding
+ * forward call.  Pairs whose scaled FP32 sum falls below the plan's rescue
+ * threshold (or overflows) are redone in FP64 (Section III-C's two-level
+ * precision), and only pairs below the FP64 floor (log10 L < about -608) get
+ * NaN gradients; pairs with u_p = 0 contribute nothing and are skipped.  The
+ * gradient buffer is overwritten.  Reads longer than 319 bases give
+ * PH_ERR_UNSUPPORTED.  Sums over pairs sharing a read use float atomics, so
+ * the last bits of a gradient may depend on completion order. */
 ph_status ph_backward_batch(ph_plan *plan, const ph_problem *problem,
                             const float *log10_params, const double *grad_log10L,
                             float *grad_params, void *stream);

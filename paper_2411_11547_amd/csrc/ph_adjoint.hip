@@ -19,13 +19,19 @@
 // per lane).  Memory is bounded by checkpoints:
 //  * row checkpoints: every lane stores the values of the row above its
 //    first row as it receives them (one row every K rows, every column);
-//  * column checkpoints: every kAdjC steps each lane stores its K-row state.
-// The backward walks the forward steps in reverse, kAdjC at a time: each
-// lane reloads its state at the start of the block, recomputes the block's
-// kAdjC columns in registers from the stored row above (no lane exchange is
-// needed for that), then runs the reverse wavefront over them.  All lanes
-// sit at the same forward step (each on its own column), so the block
-// structure is the same in every lane.
+//  * column checkpoints: every CB steps each lane stores its K-row state.
+// The backward walks the forward steps in reverse, CB at a time: each lane
+// reloads its state at the start of the block, recomputes the block's CB
+// columns in registers from the stored row above (no lane exchange is needed
+// for that), then runs the reverse wavefront over them.  All lanes sit at
+// the same forward step (each on its own column), so the block structure is
+// the same in every lane.
+//
+// Precision (the two-level scheme of Section III-C carried over to the
+// adjoint): an FP32 pass handles every pair; a pair whose scaled FP32 sum
+// leaves the FP32 range is queued by read-length class and redone by an FP64
+// pass (64 lanes per pair, one pair at a time per workgroup, checkpoints in a
+// fixed per-workgroup slice of an FP64 workspace).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -44,59 +50,87 @@ hipError_t upload_luts_adjoint()
     return hipMemcpyToSymbol(HIP_SYMBOL(c_prob), t, sizeof(t));
 }
 
-template <int P, int K>
+// Scaling of the two precisions.  The forward starts from D(0,j) = 2^kFwd / n.
+// The backward is seeded with B(m,.) = 2^(kProd - ilogb(L_s)), L_s the scaled
+// likelihood: every product F(i,j) B(i,j) counts path mass through one cell,
+// so it stays below about 2^kProd, and B itself stays below 2^SB (the
+// continuation mass of a cell is at most 1), which the range floor of each
+// precision keeps finite.
+template <typename T>
+struct AdjRange;
+template <>
+struct AdjRange<float> {
+    static constexpr int kFwd = 120, kProd = 30;
+};
+template <>
+struct AdjRange<double> {
+    static constexpr int kFwd = 1020, kProd = 20;
+};
+
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<float> {
+    using V = float2;
+};
+template <>
+struct Pair2<double> {
+    using V = double2;
+};
+
+template <typename T, int P, int K>
 struct AdjCfg {
     static constexpr int G = 64 / P;
     // E[code][row][lane] = (lam, w) with w = 1 for a mismatch, 0 otherwise
-    static constexpr int CODE_BYTES = K * 512;
+    static constexpr int ENT = 2 * (int)sizeof(T);
+    static constexpr int ROW_BYTES = 64 * ENT;
+    static constexpr int CODE_BYTES = K * ROW_BYTES;
     static constexpr int E_BYTES = kCodes * CODE_BYTES;
 };
 
-// Per-pair prologue shared by both kernels: the pair's record, the per-row
-// parameters of the lane's K rows (absorbing rows past the read end, as in
-// the forward sweep), the (lam, w) table and the haplotype staged in LDS
-// with PAD outside columns 1..n.
-template <int P, int K>
+// Per-pair state shared by the forward and backward parts: the record, the
+// per-row parameters of the lane's K rows (absorbing rows past the read end,
+// as in the forward sweep), the (lam, w) table and the haplotype staged in
+// LDS with PAD outside columns 1..n.
+template <typename T, int P, int K>
 struct AdjPair {
-    using C = AdjCfg<P, K>;
-    int lane, g, t, idx;
-    bool valid;
+    using C = AdjCfg<T, P, K>;
+    using V2 = typename Pair2<T>::V;
+    int lane, g, t;
     AdjRec rec;
     int64_t ro;
     int m, n, S;
-    float al[K], be[K], de[K], ep[K], ze[K];
+    T al[K], be[K], de[K], ep[K], ze[K];
     char *E;
     const uint8_t *hs;  // staged codes; column j sits at hs[j + P]
 
-    __device__ __forceinline__ void init(const AdjArgs &A, char *lds)
+    // S: forward steps of the pair's group (a multiple of the checkpoint
+    // block); hs_bytes: LDS bytes per group for the staged haplotype.
+    __device__ __forceinline__ void init(const AdjArgs &A, char *lds, const AdjRec &r_in, int S_in, int hs_bytes)
     {
         lane = threadIdx.x;
         g = lane / P;
         t = lane % P;
-        const int first = blockIdx.x * C::G;
-        idx = first + g;
-        valid = idx < A.nrec;
-        // groups past the end of the list mirror group 0 and never write
-        rec = A.recs[valid ? idx : first];
-        S = __builtin_amdgcn_readlane(rec.S, 0);
+        rec = r_in;
+        S = S_in;
         const DevProblem &pb = A.pb;
         ro = pb.read_offset[rec.read];
         m = (int)(pb.read_offset[rec.read + 1] - ro);
         n = rec.n;
         E = lds;
-        char *mine = E + lane * 8;
-        auto slot = [&](int c, int r) -> float * { return (float *)(mine + c * C::CODE_BYTES + r * 512); };
+        char *mine = E + lane * C::ENT;
+        auto slot = [&](int c, int r) -> T * { return (T *)(mine + c * C::CODE_BYTES + r * C::ROW_BYTES); };
 #pragma unroll 1
         for (int r = 0; r < K; ++r) {
             const int i = t * K + r;
             const int ic = min(i, m - 1);
             const RowPar p = load_row(pb, A.lin_params, ro + ic, c_prob);
             const bool real = i < m;
-            *slot(0, r) = real ? (float)p.a : 0.f;
-            *slot(1, r) = real ? (float)p.b : 0.f;
-            *slot(2, r) = real ? (float)p.d : (i == m ? 1.f : 0.f);
-            *slot(3, r) = real ? (float)p.e : 1.f;
-            *slot(4, r) = real ? (float)p.z : 0.f;
+            *slot(0, r) = real ? (T)p.a : (T)0;
+            *slot(1, r) = real ? (T)p.b : (T)0;
+            *slot(2, r) = real ? (T)p.d : (i == m ? (T)1 : (T)0);
+            *slot(3, r) = real ? (T)p.e : (T)1;
+            *slot(4, r) = real ? (T)p.z : (T)0;
         }
 #pragma unroll
         for (int r = 0; r < K; ++r) {
@@ -116,12 +150,17 @@ struct AdjPair {
 #pragma unroll
             for (int c = 0; c < kCodes; ++c) {
                 const bool match = code == (uint32_t)c || code == 4u || c == 4;
-                float2 v = make_float2(0.f, 0.f);
-                if (real && c != kPad) v = match ? make_float2((float)p.lm, 0.f) : make_float2((float)p.lx, 1.f);
-                *(float2 *)(mine + c * C::CODE_BYTES + r * 512) = v;
+                V2 v;
+                v.x = (T)0;
+                v.y = (T)0;
+                if (real && c != kPad) {
+                    v.x = match ? (T)p.lm : (T)p.lx;
+                    v.y = match ? (T)0 : (T)1;
+                }
+                *(V2 *)(mine + c * C::CODE_BYTES + r * C::ROW_BYTES) = v;
             }
         }
-        uint8_t *h = (uint8_t *)(lds + C::E_BYTES + g * A.hs_bytes);
+        uint8_t *h = (uint8_t *)(lds + C::E_BYTES + g * hs_bytes);
         const uint8_t *hap = pb.hap_bases + pb.hap_offset[rec.hap];
         const int len = S + P + 2;
         for (int x = t; x < len; x += P) {
@@ -134,7 +173,7 @@ struct AdjPair {
 
     __device__ __forceinline__ const char *ecol(int s) const
     {
-        return E + (int)hs[s - t + 1 + P] * C::CODE_BYTES + lane * 8;
+        return E + (int)hs[s - t + 1 + P] * C::CODE_BYTES + lane * C::ENT;
     }
 };
 
@@ -142,20 +181,18 @@ struct AdjPair {
 // Eq. (1)-(3) (D kept unscaled, as the gradients need it): (mo, io, do_)
 // hold column j-1 on entry, (mn, in, dn) receive column j; (mu, iu) and
 // (md, id, dd) are the row above at columns j and j-1.
-template <int K>
-__device__ __forceinline__ void adj_cell_step(const float (&mo)[K], const float (&io)[K], const float (&do_)[K],
-                                              float (&mn)[K], float (&in)[K], float (&dn)[K], float mu,
-                                              float iu, float md, float id, float dd, const float *lam,
-                                              const float (&al)[K], const float (&be)[K],
-                                              const float (&de)[K], const float (&ep)[K],
-                                              const float (&ze)[K])
+template <typename T, int K>
+__device__ __forceinline__ void adj_cell_step(const T (&mo)[K], const T (&io)[K], const T (&do_)[K], T (&mn)[K],
+                                              T (&in)[K], T (&dn)[K], T mu, T iu, T md, T id, T dd, const T *lam,
+                                              const T (&al)[K], const T (&be)[K], const T (&de)[K],
+                                              const T (&ep)[K], const T (&ze)[K])
 {
 #pragma unroll
     for (int r = 0; r < K; ++r) {
-        const float x = fma(al[r], md, be[r] * (id + dd));
-        const float mr = lam[r] * x;
-        const float ir = fma(ep[r], iu, de[r] * mu);
-        const float dr = fma(ep[r], do_[r], ze[r] * mo[r]);
+        const T x = fma(al[r], md, be[r] * (id + dd));
+        const T mr = lam[r] * x;
+        const T ir = fma(ep[r], iu, de[r] * mu);
+        const T dr = fma(ep[r], do_[r], ze[r] * mo[r]);
         md = mo[r];
         id = io[r];
         dd = do_[r];
@@ -167,35 +204,28 @@ __device__ __forceinline__ void adj_cell_step(const float (&mo)[K], const float 
     }
 }
 
-// Checkpointed forward: also writes the row above every lane at every step
-// (slot s+1 = step s, slot 0 = the initial diagonal) and every lane's state
-// before steps 0, kAdjC, 2 kAdjC, ...  Workspace of a group at ws + ws_off:
-// [S+1][3][P] row checkpoints, then [S/kAdjC][3][K][P] column checkpoints.
-template <int P, int K>
-__global__ __launch_bounds__(64) void k_adj_fwd(AdjArgs A)
+// Checkpointed forward.  Workspace of one pair: [S+1][3][P] row checkpoints
+// (slot s+1 = the row above as received at step s, slot 0 = the initial
+// diagonal), then [S/CB][3][K][P] column checkpoints (lane state before
+// steps 0, CB, 2 CB, ...).  Returns, in lane P-1, the scaled row-m sum.
+template <typename T, int P, int K, int CB>
+__device__ __forceinline__ double adj_forward(const AdjPair<T, P, K> &pr, T *bnd, T *ck, bool wr)
 {
-    extern __shared__ __attribute__((aligned(16))) char lds[];
-    AdjPair<P, K> pr;
-    pr.init(A, lds);
     const int t = pr.t, S = pr.S;
-    const bool wr = pr.valid;
-    float *bnd = A.ws + pr.rec.ws_off;
-    float *ck = bnd + (int64_t)(S + 1) * 3 * P;
-    const float edge = (t == 0) ? (float)(ldexp(1.0, 120) / (double)pr.n) : 0.f;  // D(0, j) = 1/n, scaled
-
-    float M[K], I[K], D[K];
+    const T edge = (t == 0) ? (T)(ldexp(1.0, AdjRange<T>::kFwd) / (double)pr.n) : (T)0;  // D(0, j) = 1/n, scaled
+    T M[K], I[K], D[K];
 #pragma unroll
-    for (int r = 0; r < K; ++r) M[r] = I[r] = D[r] = 0.f;
-    float md = 0.f, id = 0.f, dd = edge;
+    for (int r = 0; r < K; ++r) M[r] = I[r] = D[r] = (T)0;
+    T md = 0, id = 0, dd = edge;
     if (wr) {
-        bnd[0 * P + t] = 0.f;
-        bnd[1 * P + t] = 0.f;
+        bnd[0 * P + t] = (T)0;
+        bnd[1 * P + t] = (T)0;
         bnd[2 * P + t] = dd;
     }
     double acc = 0.0;
-    for (int s0 = 0; s0 < S; s0 += kAdjC) {
+    for (int s0 = 0; s0 < S; s0 += CB) {
         if (wr) {
-            float *cq = ck + (int64_t)(s0 / kAdjC) * 3 * K * P + t;
+            T *cq = ck + (int64_t)(s0 / CB) * 3 * K * P + t;
 #pragma unroll
             for (int r = 0; r < K; ++r) {
                 cq[(0 * K + r) * P] = M[r];
@@ -204,151 +234,146 @@ __global__ __launch_bounds__(64) void k_adj_fwd(AdjArgs A)
             }
         }
 #pragma unroll
-        for (int c = 0; c < kAdjC; ++c) {
+        for (int c = 0; c < CB; ++c) {
             const int s = s0 + c;
-            const float mu = shift_up<P>(M[K - 1]);
-            const float iu = shift_up<P>(I[K - 1]);
-            const float du = shift_up<P>(D[K - 1]) + edge;
+            const T mu = shift_up<P>(M[K - 1]);
+            const T iu = shift_up<P>(I[K - 1]);
+            const T du = shift_up<P>(D[K - 1]) + edge;
             if (wr) {
-                float *b = bnd + (int64_t)(s + 1) * 3 * P + t;
+                T *b = bnd + (int64_t)(s + 1) * 3 * P + t;
                 b[0] = mu;
                 b[P] = iu;
                 b[2 * P] = du;
             }
-            float lam[K];
+            T lam[K];
             const char *e = pr.ecol(s);
 #pragma unroll
-            for (int r = 0; r < K; ++r) lam[r] = *(const float *)(e + r * 512);
-            adj_cell_step<K>(M, I, D, M, I, D, mu, iu, md, id, dd, lam, pr.al, pr.be, pr.de, pr.ep, pr.ze);
+            for (int r = 0; r < K; ++r) lam[r] = *(const T *)(e + r * AdjCfg<T, P, K>::ROW_BYTES);
+            adj_cell_step<T, K>(M, I, D, M, I, D, mu, iu, md, id, dd, lam, pr.al, pr.be, pr.de, pr.ep, pr.ze);
             md = mu;
             id = iu;
             dd = du;
             acc += (double)I[K - 1];
         }
     }
-    if (wr && t == P - 1) A.Ls[pr.idx] = acc;
+    return acc;
 }
 
-template <int P, int K>
-__device__ __forceinline__ void adj_load_block(const float *bnd, const float *ck, int q, int t, float (&cq)[3][K],
-                                               float (&bq)[kAdjC + 1][3])
+template <typename T, int P, int K, int CB>
+__device__ __forceinline__ void adj_load_block(const T *bnd, const T *ck, int q, int t, T (&cq)[3][K],
+                                               T (&bq)[CB + 1][3])
 {
-    const float *c0 = ck + (int64_t)q * 3 * K * P + t;
+    const T *c0 = ck + (int64_t)q * 3 * K * P + t;
 #pragma unroll
     for (int v = 0; v < 3; ++v)
 #pragma unroll
         for (int r = 0; r < K; ++r) cq[v][r] = c0[(v * K + r) * P];
-    const float *b0 = bnd + (int64_t)q * kAdjC * 3 * P + t;
+    const T *b0 = bnd + (int64_t)q * CB * 3 * P + t;
 #pragma unroll
-    for (int c = 0; c <= kAdjC; ++c)
+    for (int c = 0; c <= CB; ++c)
 #pragma unroll
         for (int v = 0; v < 3; ++v) bq[c][v] = b0[(c * 3 + v) * P];
 }
 
-// Backward: reverse wavefront over the checkpointed forward, gradients of
-// u_p log10 L_p added into the per-read-base gradient array.
-template <int P, int K>
-__global__ __launch_bounds__(64) void k_adj_bwd(AdjArgs A)
-{
-    extern __shared__ __attribute__((aligned(16))) char lds[];
-    AdjPair<P, K> pr;
-    pr.init(A, lds);
-    const int t = pr.t, S = pr.S;
-    const float *bnd = A.ws + pr.rec.ws_off;
-    const float *ck = bnd + (int64_t)(S + 1) * 3 * P;
+// Seven row sums of forward value x backward value, per row of the lane:
+// alpha, beta, mismatch emission, delta, eps (insert), eps (delete), zeta.
+template <typename T, int K>
+struct AdjSums {
+    T a[K], b[K], x[K], d[K], ei[K], ed[K], z[K];
+};
 
+// Reverse wavefront over the checkpointed forward of one pair.
+template <typename T, int P, int K, int CB>
+__device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T *bnd, const T *ck, T bscale,
+                                             AdjSums<T, K> &A)
+{
+    using C = AdjCfg<T, P, K>;
+    using V2 = typename Pair2<T>::V;
+    const int t = pr.t, S = pr.S;
     // parameters of the row below the lane's last row: the next lane's first
     // row, or below the group a virtual row that only passes B_I up
-    const float an_x = shift_down<P>(pr.al[0]);
-    const float bn_x = shift_down<P>(pr.be[0]);
-    const float dn_x = shift_down<P>(pr.de[0]);
-    const float en_x = shift_down<P>(pr.ep[0]) + ((t == P - 1) ? 1.f : 0.f);
+    const T an_x = shift_down<P>(pr.al[0]);
+    const T bn_x = shift_down<P>(pr.be[0]);
+    const T dn_x = shift_down<P>(pr.de[0]);
+    const T en_x = shift_down<P>(pr.ep[0]) + ((t == P - 1) ? (T)1 : (T)0);
+    const T edge_bi = (t == P - 1) ? bscale : (T)0;
 
-    // B is seeded with 2^SB, SB chosen so that forward x backward products
-    // sit near 2^30 whatever L is
-    const double Ls = A.Ls[pr.idx < A.nrec ? pr.idx : blockIdx.x * AdjCfg<P, K>::G];
-    const bool good = (Ls >= A.threshold) && (Ls <= 3.0e38);
-    const int SB = good ? 30 - ilogb(Ls) : 0;
-    const float bscale = good ? ldexpf(1.f, SB) : 0.f;
-    const float edge_bi = (t == P - 1) ? bscale : 0.f;
-
-    float BI[K], BD[K], BL[K];
-    float Aa[K], Ab[K], Am[K], Ad[K], Aei[K], Aed[K], Az[K];
+    T BI[K], BD[K], BL[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) {
-        BI[r] = BD[r] = BL[r] = 0.f;
-        Aa[r] = Ab[r] = Am[r] = Ad[r] = Aei[r] = Aed[r] = Az[r] = 0.f;
+        BI[r] = BD[r] = BL[r] = (T)0;
+        A.a[r] = A.b[r] = A.x[r] = A.d[r] = A.ei[r] = A.ed[r] = A.z[r] = (T)0;
     }
-    float bl_dn_prev = 0.f;
+    T bl_dn_prev = 0;
 
-    const int Q = S / kAdjC;
-    float cn[3][K], bn[kAdjC + 1][3];
-    adj_load_block<P, K>(bnd, ck, Q - 1, t, cn, bn);
+    const int Q = S / CB;
+    T cn[3][K], bn[CB + 1][3];
+    adj_load_block<T, P, K, CB>(bnd, ck, Q - 1, t, cn, bn);
     for (int q = Q - 1; q >= 0; --q) {
-        float F[kAdjC + 1][3][K];
-        float bb[kAdjC + 1][3];
+        T F[CB + 1][3][K];
+        T bb[CB + 1][3];
 #pragma unroll
         for (int v = 0; v < 3; ++v)
 #pragma unroll
             for (int r = 0; r < K; ++r) F[0][v][r] = cn[v][r];
 #pragma unroll
-        for (int c = 0; c <= kAdjC; ++c)
+        for (int c = 0; c <= CB; ++c)
 #pragma unroll
             for (int v = 0; v < 3; ++v) bb[c][v] = bn[c][v];
-        if (q > 0) adj_load_block<P, K>(bnd, ck, q - 1, t, cn, bn);
+        if (q > 0) adj_load_block<T, P, K, CB>(bnd, ck, q - 1, t, cn, bn);
 
         // recompute the block's columns from the lane's checkpoint
 #pragma unroll
-        for (int c = 0; c < kAdjC; ++c) {
-            float lam[K];
-            const char *e = pr.ecol(q * kAdjC + c);
+        for (int c = 0; c < CB; ++c) {
+            T lam[K];
+            const char *e = pr.ecol(q * CB + c);
 #pragma unroll
-            for (int r = 0; r < K; ++r) lam[r] = *(const float *)(e + r * 512);
-            adj_cell_step<K>(F[c][0], F[c][1], F[c][2], F[c + 1][0], F[c + 1][1], F[c + 1][2], bb[c + 1][0],
-                             bb[c + 1][1], bb[c][0], bb[c][1], bb[c][2], lam, pr.al, pr.be, pr.de, pr.ep,
-                             pr.ze);
+            for (int r = 0; r < K; ++r) lam[r] = *(const T *)(e + r * C::ROW_BYTES);
+            adj_cell_step<T, K>(F[c][0], F[c][1], F[c][2], F[c + 1][0], F[c + 1][1], F[c + 1][2], bb[c + 1][0],
+                                bb[c + 1][1], bb[c][0], bb[c][1], bb[c][2], lam, pr.al, pr.be, pr.de, pr.ep,
+                                pr.ze);
         }
 
         // reverse wavefront over the block
 #pragma unroll
-        for (int c = kAdjC - 1; c >= 0; --c) {
-            const char *e = pr.ecol(q * kAdjC + c);
-            float lam[K], w[K];
+        for (int c = CB - 1; c >= 0; --c) {
+            const char *e = pr.ecol(q * CB + c);
+            T lam[K], w[K];
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const float2 v = *(const float2 *)(e + r * 512);
+                const V2 v = *(const V2 *)(e + r * C::ROW_BYTES);
                 lam[r] = v.x;
                 w[r] = v.y;
             }
-            const float bi_dn = shift_down<P>(BI[0]) + edge_bi;
-            const float bl_dn = shift_down<P>(BL[0]);
-            float bid = bi_dn;          // B_I of the row below, this column
-            float bl_below = bl_dn_prev; // Bl of the row below, next column
+            const T bi_dn = shift_down<P>(BI[0]) + edge_bi;
+            const T bl_dn = shift_down<P>(BL[0]);
+            T bid = bi_dn;            // B_I of the row below, this column
+            T bl_below = bl_dn_prev;  // Bl of the row below, next column
 #pragma unroll
             for (int r = K - 1; r >= 0; --r) {
-                const float bld = bl_below;
-                const float an = (r == K - 1) ? an_x : pr.al[r + 1];
-                const float bnr = (r == K - 1) ? bn_x : pr.be[r + 1];
-                const float dn = (r == K - 1) ? dn_x : pr.de[r + 1];
-                const float en = (r == K - 1) ? en_x : pr.ep[r + 1];
-                const float tb = bnr * bld;
-                const float bi = fma(en, bid, tb);
-                const float bd = fma(pr.ep[r], BD[r], tb);
-                const float bm = fma(an, bld, fma(dn, bid, pr.ze[r] * BD[r]));
-                const float bl = lam[r] * bm;
+                const T bld = bl_below;
+                const T an = (r == K - 1) ? an_x : pr.al[r + 1];
+                const T bnr = (r == K - 1) ? bn_x : pr.be[r + 1];
+                const T dn = (r == K - 1) ? dn_x : pr.de[r + 1];
+                const T en = (r == K - 1) ? en_x : pr.ep[r + 1];
+                const T tb = bnr * bld;
+                const T bi = fma(en, bid, tb);
+                const T bd = fma(pr.ep[r], BD[r], tb);
+                const T bm = fma(an, bld, fma(dn, bid, pr.ze[r] * BD[r]));
+                const T bl = lam[r] * bm;
                 // forward values around (i, j): row above at j and j-1, own row at j-1 and j
-                const float mu = (r == 0) ? bb[c + 1][0] : F[c + 1][0][r - 1];
-                const float iu = (r == 0) ? bb[c + 1][1] : F[c + 1][1][r - 1];
-                const float mdg = (r == 0) ? bb[c][0] : F[c][0][r - 1];
-                const float idg = (r == 0) ? bb[c][1] : F[c][1][r - 1];
-                const float ddg = (r == 0) ? bb[c][2] : F[c][2][r - 1];
-                Aa[r] = fma(mdg, bl, Aa[r]);
-                Ab[r] = fma(idg + ddg, bl, Ab[r]);
-                Am[r] = fma(w[r] * F[c + 1][0][r], bm, Am[r]);
-                Ad[r] = fma(mu, bi, Ad[r]);
-                Aei[r] = fma(iu, bi, Aei[r]);
-                Aed[r] = fma(F[c][2][r], bd, Aed[r]);
-                Az[r] = fma(F[c][0][r], bd, Az[r]);
+                const T mu = (r == 0) ? bb[c + 1][0] : F[c + 1][0][r - 1];
+                const T iu = (r == 0) ? bb[c + 1][1] : F[c + 1][1][r - 1];
+                const T mdg = (r == 0) ? bb[c][0] : F[c][0][r - 1];
+                const T idg = (r == 0) ? bb[c][1] : F[c][1][r - 1];
+                const T ddg = (r == 0) ? bb[c][2] : F[c][2][r - 1];
+                A.a[r] = fma(mdg, bl, A.a[r]);
+                A.b[r] = fma(idg + ddg, bl, A.b[r]);
+                A.x[r] = fma(w[r] * F[c + 1][0][r], bm, A.x[r]);
+                A.d[r] = fma(mu, bi, A.d[r]);
+                A.ei[r] = fma(iu, bi, A.ei[r]);
+                A.ed[r] = fma(F[c][2][r], bd, A.ed[r]);
+                A.z[r] = fma(F[c][0][r], bd, A.z[r]);
                 bl_below = BL[r];  // still the next column's value: row r-1's diagonal
                 BI[r] = bi;
                 BD[r] = bd;
@@ -358,34 +383,133 @@ __global__ __launch_bounds__(64) void k_adj_bwd(AdjArgs A)
             bl_dn_prev = bl_dn;
         }
     }
+}
 
-    // expected uses per row: g = coefficient x sum / (L_s 2^SB), times the
-    // upstream gradient of the pair; lam_match by sum over the row's M entries
-    if (!pr.valid) return;
-    const double u = A.grad_in[pr.rec.out];
-    if (u == 0.0) return;  // contributes nothing, even where the FP32 sweep underflowed
-    const double inv = good ? 1.0 / ldexp(Ls, SB) : (double)NAN;
+// Expected uses per row, g = coefficient x sum / (L_s 2^SB) (lam_match by
+// sum over the row's M entries), times the pair's upstream gradient u, added
+// into the per-read-base gradient array.
+template <typename T, int P, int K>
+__device__ __forceinline__ void adj_emit(const AdjArgs &A, const AdjPair<T, P, K> &pr, double u, double inv,
+                                         const AdjSums<T, K> &s)
+{
 #pragma unroll
     for (int r = 0; r < K; ++r) {
-        const int i = t * K + r;
+        const int i = pr.t * K + r;
         if (i >= pr.m) continue;
-        const double ga = pr.al[r] * (double)Aa[r] * inv;
-        const double gb = pr.be[r] * (double)Ab[r] * inv;
-        const double gx = (double)Am[r] * inv;
+        const double ga = (double)pr.al[r] * (double)s.a[r] * inv;
+        const double gb = (double)pr.be[r] * (double)s.b[r] * inv;
+        const double gx = (double)s.x[r] * inv;
         float *o = A.grad_out + (pr.ro + i) * 7;
         atomicAdd(o + 0, (float)(u * ga));
         atomicAdd(o + 1, (float)(u * gb));
-        atomicAdd(o + 2, (float)(u * pr.de[r] * (double)Ad[r] * inv));
-        atomicAdd(o + 3, (float)(u * pr.ep[r] * ((double)Aei[r] + (double)Aed[r]) * inv));
-        atomicAdd(o + 4, (float)(u * pr.ze[r] * (double)Az[r] * inv));
+        atomicAdd(o + 2, (float)(u * (double)pr.de[r] * (double)s.d[r] * inv));
+        atomicAdd(o + 3, (float)(u * (double)pr.ep[r] * ((double)s.ei[r] + (double)s.ed[r]) * inv));
+        atomicAdd(o + 4, (float)(u * (double)pr.ze[r] * (double)s.z[r] * inv));
         atomicAdd(o + 5, (float)(u * (ga + gb - gx)));
         atomicAdd(o + 6, (float)(u * gx));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 pass: one workgroup per tile of G pairs (every group of a tile uses
+// the tile's step count S, that of its first, longest record); the
+// checkpoints of a chunk of tiles live in A.ws.  Groups past the end of the
+// record list mirror group 0 and never write.
+// ---------------------------------------------------------------------------
+template <int P, int K>
+__global__ __launch_bounds__(64) void k_adj_fwd(AdjArgs A)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    constexpr int G = 64 / P;
+    const int first = blockIdx.x * G, idx = first + (int)threadIdx.x / P;
+    const bool valid = idx < A.nrec;
+    const AdjRec rec = A.recs[valid ? idx : first];
+    AdjPair<float, P, K> pr;
+    pr.init(A, lds, rec, __builtin_amdgcn_readlane(rec.S, 0), A.hs_bytes);
+    float *bnd = A.ws + rec.ws_off;
+    float *ck = bnd + (int64_t)(pr.S + 1) * 3 * P;
+    const double acc = adj_forward<float, P, K, kAdjC>(pr, bnd, ck, valid);
+    if (valid && pr.t == P - 1) A.Ls[idx] = acc;
+}
+
+template <int P, int K>
+__global__ __launch_bounds__(64) void k_adj_bwd(AdjArgs A)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    constexpr int G = 64 / P;
+    const int first = blockIdx.x * G, idx = first + (int)threadIdx.x / P;
+    const bool valid = idx < A.nrec;
+    const AdjRec rec = A.recs[valid ? idx : first];
+    AdjPair<float, P, K> pr;
+    pr.init(A, lds, rec, __builtin_amdgcn_readlane(rec.S, 0), A.hs_bytes);
+    const float *bnd = A.ws + rec.ws_off;
+    const float *ck = bnd + (int64_t)(pr.S + 1) * 3 * P;
+    const double Ls = A.Ls[valid ? idx : first];
+    const bool good = (Ls >= A.threshold) && (Ls <= 3.0e38);
+    const int SB = good ? AdjRange<float>::kProd - ilogb(Ls) : 0;
+    AdjSums<float, K> sums;
+    adj_backward<float, P, K, kAdjC>(pr, bnd, ck, good ? ldexpf(1.f, SB) : 0.f, sums);
+    if (!valid) return;
+    const double u = A.grad_in[rec.out];
+    if (u == 0.0) return;  // contributes nothing, whatever the pair's range
+    if (!good) {
+        // outside the FP32 range: queued for the FP64 pass, class K64 - 1 with
+        // K64 = ceil((m + 1) / 64) rows per lane
+        if (pr.t == 0) {
+            const int cls = (pr.m + 64) / 64 - 1;
+            const int slot = atomicAdd(&A.q64_count[cls], 1);
+            A.q64[(int64_t)cls * A.q64_stride + slot] = (int32_t)(A.rec_base + idx);
+        }
+        return;
+    }
+    adj_emit<float, P, K>(A, pr, u, 1.0 / ldexp(Ls, SB), sums);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 pass: a persistent grid drains the queue of class K (64 lanes x K
+// rows, reads of 64 (K-1) .. 64 K - 1 bases); workgroup b owns the slice
+// [b ws64_stride, (b+1) ws64_stride) of A.ws64 and one pair at a time.
+// Every wave leaves the loop once the shared cursor passes the queue length.
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(64) void k_adj64(AdjArgs A)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    constexpr int P = 64;
+    const int cls = K - 1;
+    const int count = A.q64_count[cls];
+    double *bnd = A.ws64 + (int64_t)blockIdx.x * A.ws64_stride;
+    for (;;) {
+        int item = 0;
+        if (threadIdx.x == 0) item = atomicAdd(&A.q64_next[cls], 1);
+        item = __builtin_amdgcn_readlane(item, 0);
+        if (item >= count) break;
+        const int32_t gi = A.q64[(int64_t)cls * A.q64_stride + item];
+        const AdjRec rec = A.all_recs[gi];
+        const int S = ((rec.n + P - 1 + kAdjC64 - 1) / kAdjC64) * kAdjC64;
+        AdjPair<double, P, K> pr;
+        pr.init(A, lds, rec, S, A.hs_bytes64);
+        double *ck = bnd + (int64_t)(S + 1) * 3 * P;
+        const double acc = adj_forward<double, P, K, kAdjC64>(pr, bnd, ck, true);
+        const double Ls = __shfl(acc, P - 1);
+        // below the FP64 range floor the pair's gradients are NaN
+        const bool good = (Ls >= A.floor64) && isfinite(Ls);
+        const int SB = good ? AdjRange<double>::kProd - ilogb(Ls) : 0;
+        AdjSums<double, K> sums;
+        adj_backward<double, P, K, kAdjC64>(pr, bnd, ck, good ? ldexp(1.0, SB) : 0.0, sums);
+        adj_emit<double, P, K>(A, pr, A.grad_in[rec.out], good ? 1.0 / ldexp(Ls, SB) : (double)NAN, sums);
+        __syncthreads();  // LDS tables are rebuilt for the next pair
     }
 }
 
 __global__ __launch_bounds__(256) void k_zero_f32(float *p, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0.f;
+}
+
+__global__ __launch_bounds__(64) void k_zero_i32(int32_t *p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += 64) p[i] = 0;
 }
 
 #define PH_ADJ_CONFIGS(X) X(32, 1) X(32, 2) X(32, 3) X(32, 4) X(32, 5) X(64, 3) X(64, 4) X(64, 5)
@@ -400,24 +524,40 @@ bool adj_supported(int P, int K)
 
 int adj_e_bytes(int P, int K)
 {
-    (void)P;
-    return kCodes * K * 512;
+    (void)P;  // the table holds all 64 lanes of the wave whatever the group size
+    return kCodes * K * AdjCfg<float, 64, 1>::ROW_BYTES;
 }
+
+int adj64_e_bytes(int K) { return kCodes * K * AdjCfg<double, 64, 1>::ROW_BYTES; }
 
 hipError_t launch_adj(const AdjArgs &a, int P, int K, int tiles, bool backward, hipStream_t s)
 {
-    const size_t lds = (size_t)kCodes * K * 512 + (size_t)(64 / P) * a.hs_bytes;
-#define PH_LA(p, k)                                                                                 \
-    if (P == p && K == k) {                                                                         \
-        if (backward)                                                                               \
-            hipLaunchKernelGGL((k_adj_bwd<p, k>), dim3(tiles), dim3(64), lds, s, a);                \
-        else                                                                                        \
-            hipLaunchKernelGGL((k_adj_fwd<p, k>), dim3(tiles), dim3(64), lds, s, a);                \
-        return hipGetLastError();                                                                   \
+    const size_t lds = (size_t)adj_e_bytes(P, K) + (size_t)(64 / P) * a.hs_bytes;
+#define PH_LA(p, k)                                                                  \
+    if (P == p && K == k) {                                                          \
+        if (backward)                                                                \
+            hipLaunchKernelGGL((k_adj_bwd<p, k>), dim3(tiles), dim3(64), lds, s, a); \
+        else                                                                         \
+            hipLaunchKernelGGL((k_adj_fwd<p, k>), dim3(tiles), dim3(64), lds, s, a); \
+        return hipGetLastError();                                                    \
     }
     PH_ADJ_CONFIGS(PH_LA)
 #undef PH_LA
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj64(const AdjArgs &a, int K, int grid, hipStream_t s)
+{
+    const size_t lds = (size_t)adj64_e_bytes(K) + (size_t)a.hs_bytes64;
+    switch (K) {
+    case 1: hipLaunchKernelGGL(k_adj64<1>, dim3(grid), dim3(64), lds, s, a); break;
+    case 2: hipLaunchKernelGGL(k_adj64<2>, dim3(grid), dim3(64), lds, s, a); break;
+    case 3: hipLaunchKernelGGL(k_adj64<3>, dim3(grid), dim3(64), lds, s, a); break;
+    case 4: hipLaunchKernelGGL(k_adj64<4>, dim3(grid), dim3(64), lds, s, a); break;
+    case 5: hipLaunchKernelGGL(k_adj64<5>, dim3(grid), dim3(64), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s)
@@ -426,6 +566,12 @@ hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s)
     if (g < 1) g = 1;
     if (g > 8192) g = 8192;
     hipLaunchKernelGGL(k_zero_f32, dim3((int)g), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int32_t *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, p, n);
     return hipGetLastError();
 }
 

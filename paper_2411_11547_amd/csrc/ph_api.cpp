@@ -67,6 +67,8 @@ std::once_flag g_lut_adj_once;
 hipError_t g_lut_adj_status = hipSuccess;
 
 constexpr int64_t kAdjWsFloats = (int64_t)1 << 29;  // 2 GiB of checkpoints per chunk
+constexpr int64_t kAdjWs64Doubles = (int64_t)1 << 28;  // 2 GiB for the FP64 pass
+constexpr int kAdj64MaxGrid = 1024;                   // FP64 pass: 4 workgroups per CU
 
 int rescue_class_of(int m) { return m < 128 ? 0 : m < 256 ? 1 : m < 512 ? 2 : 3; }
 
@@ -176,6 +178,14 @@ struct ph_plan {
     AdjRec *d_adj_recs = nullptr;
     double *d_adj_Ls = nullptr;
     float *d_ws = nullptr;
+    // FP64 pass over the pairs the FP32 pass leaves out: queues per class,
+    // [2][kAdj64Classes] counters (lengths, cursors), per-workgroup checkpoints
+    int32_t *d_q64 = nullptr;
+    int32_t *d_q64_cnt = nullptr;
+    double *d_ws64 = nullptr;
+    int64_t q64_stride = 0, ws64_stride = 0;
+    int32_t grid64 = 0, hs_bytes64 = 0;
+    bool class64[kAdj64Classes] = {};
     hipEvent_t ev_adj[2] = {};
     bool adj_recorded = false;
 };
@@ -190,7 +200,7 @@ void free_plan(ph_plan *p)
         if (p->graph[i]) (void)hipGraphDestroy(p->graph[i]);
     }
     void *bufs[] = {p->d_out_offset, p->d_m2bin, p->d_bin_G, p->d_hist, p->d_recs, p->d_book, p->d_rescue, p->d_lin,
-                    p->d_adj_recs, p->d_adj_Ls, p->d_ws};
+                    p->d_adj_recs, p->d_adj_Ls, p->d_ws, p->d_q64, p->d_q64_cnt, p->d_ws64};
     for (auto &e : p->ev_adj)
         if (e) (void)hipEventDestroy(e);
     for (void *b : bufs)
@@ -326,10 +336,36 @@ ph_status build_adjoint(ph_plan *p)
             return p->adj_status;
         }
     }
+    // FP64 pass: sized for the longest haplotype and the largest class of
+    // the plan; the grid is bounded by the workspace budget
+    int n_max = 1, k64_max = 1;
+    for (const auto &it : items) n_max = std::max(n_max, it.r.n);
+    for (int32_t r = 0; r < p->nr; ++r) {
+        const int m = (int)(p->h_ro[r + 1] - p->h_ro[r]);
+        const int k = (m + 64) / 64;
+        if (k >= 1 && k <= kAdj64Classes) {
+            p->class64[k - 1] = true;
+            k64_max = std::max(k64_max, k);
+        }
+    }
+    const int S64 = ((n_max + 63 + kAdjC64 - 1) / kAdjC64) * kAdjC64;
+    p->hs_bytes64 = ((S64 + 64 + 2 + 15) / 16) * 16;
+    if ((int64_t)adj64_e_bytes(k64_max) + p->hs_bytes64 > 64 * 1024) {
+        p->adj_status = PH_ERR_UNSUPPORTED;
+        p->adj_error = "haplotype too long for the FP64 adjoint sweep";
+        return p->adj_status;
+    }
+    p->ws64_stride = (((int64_t)(S64 + 1) * 3 + (int64_t)(S64 / kAdjC64) * 3 * k64_max) * 64 + 31) / 32 * 32;
+    p->grid64 = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>({(int64_t)kAdj64MaxGrid, kAdjWs64Doubles / p->ws64_stride, (int64_t)items.size()}));
+    p->q64_stride = (int64_t)items.size();
     ph_status st;
     if ((st = dalloc(&p->d_adj_recs, recs.size()))) return p->adj_status = st;
     if ((st = dalloc(&p->d_adj_Ls, recs.size()))) return p->adj_status = st;
     if ((st = dalloc(&p->d_ws, (size_t)std::max<int64_t>(ws_max, 1)))) return p->adj_status = st;
+    if ((st = dalloc(&p->d_q64, (size_t)kAdj64Classes * p->q64_stride))) return p->adj_status = st;
+    if ((st = dalloc(&p->d_q64_cnt, (size_t)2 * kAdj64Classes))) return p->adj_status = st;
+    if ((st = dalloc(&p->d_ws64, (size_t)p->grid64 * p->ws64_stride))) return p->adj_status = st;
     hipError_t e = hipMemcpy(p->d_adj_recs, recs.data(), recs.size() * sizeof(AdjRec), hipMemcpyHostToDevice);
     if (e != hipSuccess) return p->adj_status = fail(PH_ERR_HIP, "hipMemcpy: %s", hipGetErrorString(e));
     return PH_OK;
@@ -722,6 +758,7 @@ ph_status ph_backward_batch(ph_plan *p, const ph_problem *pb, const float *log10
     HIPCHK(hipEventRecord(p->ev_adj[0], s));
     if (log10_params) HIPCHK(launch_prep_params(log10_params, p->nread_bases, p->d_lin, s));
     HIPCHK(launch_zero_f32(grad_params, p->nread_bases * 7, s));
+    HIPCHK(launch_zero_i32(p->d_q64_cnt, 2 * kAdj64Classes, s));
     AdjArgs a{};
     a.pb.read_offset = pb->read_offset;
     a.pb.read_bases = pb->read_bases;
@@ -736,14 +773,28 @@ ph_status ph_backward_batch(ph_plan *p, const ph_problem *pb, const float *log10
     a.grad_in = grad_log10L;
     a.grad_out = grad_params;
     a.threshold = p->threshold;
+    a.all_recs = p->d_adj_recs;
+    a.q64 = p->d_q64;
+    a.q64_stride = p->q64_stride;
+    a.q64_count = p->d_q64_cnt;
+    a.q64_next = p->d_q64_cnt + kAdj64Classes;
+    a.ws64 = p->d_ws64;
+    a.ws64_stride = p->ws64_stride;
+    a.hs_bytes64 = p->hs_bytes64;
+    a.floor64 = std::ldexp(1.0, -1000);
     for (const auto &ch : p->adj_chunks) {
         a.recs = p->d_adj_recs + ch.rec_begin;
+        a.rec_base = ch.rec_begin;
         a.Ls = p->d_adj_Ls + ch.rec_begin;
         a.nrec = ch.nrec;
         a.hs_bytes = ch.hs_bytes;
         HIPCHK(launch_adj(a, ch.P, ch.K, ch.tiles, false, s));
         HIPCHK(launch_adj(a, ch.P, ch.K, ch.tiles, true, s));
     }
+    // pairs out of the FP32 range, per class (a class whose queue stayed
+    // empty exits at once)
+    for (int k = 1; k <= kAdj64Classes; ++k)
+        if (p->class64[k - 1]) HIPCHK(launch_adj64(a, k, p->grid64, s));
     HIPCHK(hipEventRecord(p->ev_adj[1], s));
     p->adj_recorded = true;
     return PH_OK;

@@ -88,7 +88,9 @@ struct SweepArgs {
 
 // Adjoint: one record per pair, grouped by (P, K) and tiled G = 64/P pairs
 // at a time; every group of a tile uses the tile's step count S.
-constexpr int kAdjC = 4;  // forward steps per column checkpoint block
+constexpr int kAdjC = 4;    // FP32: forward steps per column checkpoint block
+constexpr int kAdjC64 = 2;  // FP64: forward steps per column checkpoint block
+constexpr int kAdj64Classes = 5;  // FP64 adjoint: 64 lanes x 1..5 rows
 
 struct AdjRec {
     int32_t read, hap, out, n;
@@ -100,13 +102,24 @@ struct AdjArgs {
     DevProblem pb;
     const double *lin_params;
     const AdjRec *recs;   // records of one chunk of one configuration
+    int64_t rec_base;     // index of recs[0] in all_recs
     int32_t nrec;
     int32_t hs_bytes;     // LDS bytes per group for the staged haplotype
     float *ws;            // checkpoints of the chunk
     double *Ls;           // per record: scaled FP32 row-m sum
     const double *grad_in;  // per output pair
     float *grad_out;        // per read base x 7
-    double threshold;
+    double threshold;       // FP32 scaled-sum range floor
+    // FP64 pass over the pairs the FP32 pass left out
+    const AdjRec *all_recs;
+    int32_t *q64;           // [kAdj64Classes][q64_stride] indices into all_recs
+    int64_t q64_stride;
+    int32_t *q64_count;     // [kAdj64Classes] queue lengths
+    int32_t *q64_next;      // [kAdj64Classes] work cursors
+    double *ws64;           // [grid][ws64_stride] per-workgroup checkpoints
+    int64_t ws64_stride;
+    int32_t hs_bytes64;
+    double floor64;         // FP64 scaled-sum range floor
 };
 
 hipError_t upload_luts_adjoint();
@@ -114,6 +127,9 @@ bool adj_supported(int P, int K);
 int adj_e_bytes(int P, int K);
 hipError_t launch_adj(const AdjArgs &a, int P, int K, int tiles, bool backward, hipStream_t s);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
+hipError_t launch_zero_i32(int32_t *p, int n, hipStream_t s);
+int adj64_e_bytes(int K);
+hipError_t launch_adj64(const AdjArgs &a, int K, int grid, hipStream_t s);
 
 // Launchers (ph_kernels.hip).  All enqueue on `s` and return the HIP status.
 hipError_t upload_luts();

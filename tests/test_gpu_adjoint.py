@@ -72,8 +72,10 @@ def test_adjoint_shared_reads_weighted():
     compare(got, ref, "config1x3")
 
 
-def test_adjoint_ragged_lengths():
-    say("adjoint, read lengths across every configuration")
+def ragged_problem():
+    """Reads of lengths at every adjoint configuration edge against
+    haplotypes of 1..700 bases (prefixes of the reads' reference): many
+    pairs are far outside the FP32 range."""
     rng = np.random.default_rng(2)
     reads, haps = [], []
     ref_seq = rng.choice(list("ACGT"), size=700)
@@ -90,14 +92,69 @@ def test_adjoint_ragged_lengths():
     prob.ins_qual[:] = rng.integers(25, 46, size=len(prob.ins_qual))
     prob.del_qual[:] = rng.integers(25, 46, size=len(prob.del_qual))
     prob.gcp_qual[:] = rng.integers(5, 20, size=len(prob.gcp_qual))
-    u = np.ones(prob.num_pairs)
+    return prob
+
+
+# log10 L below which the FP64 adjoint reports NaN (scaled sum under 2^-1000
+# with the 2^1020 start: -2020 log10 2 = -608.1); tests keep a margin
+FP64_FLOOR_LOG10 = -600.0
+
+
+def test_adjoint_ragged_lengths():
+    """Every pair above the FP64 floor, FP32 and FP64 passes mixed."""
+    say("adjoint, read lengths across every configuration, both precisions")
+    prob = ragged_problem()
     lf = oracle.forward(prob)
-    keep = lf > -60  # pairs the FP32 sweep handles
-    u[~keep] = 0.0
+    u = np.where(lf > FP64_FLOOR_LOG10, 1.0, 0.0)
+    say(f"  {int((lf < -64).sum())} of {prob.num_pairs} pairs below the FP32 range, "
+        f"{int((u == 0).sum())} below the FP64 floor (u = 0)")
+    assert (lf < -64).sum() >= 10 and (u == 1).sum() >= 50
     ref, _ = oracle_grad(prob, u)
     got, _ = gpu_grad(prob, u)
-    # rows whose only pairs were dropped get NaN on the GPU only if u != 0; u = 0 rows stay finite
     compare(got, ref, "ragged")
+
+
+def test_adjoint_fp64_forced_every_pair():
+    """A rescue threshold of +inf sends every pair to the FP64 pass (all five
+    read-length classes of the ragged set)."""
+    say("adjoint, FP64 pass forced for every pair")
+    prob = ragged_problem()
+    lf = oracle.forward(prob)
+    u = np.where(lf > FP64_FLOOR_LOG10, np.random.default_rng(7).uniform(0.5, 1.5, prob.num_pairs), 0.0)
+    ref, _ = oracle_grad(prob, u)
+    got, _ = gpu_grad(prob, u, rescue_threshold=float("inf"))
+    compare(got, ref, "fp64 forced")
+
+
+def test_adjoint_fp64_precision_stress():
+    """Pairs of the precision-stress workload (250 bp reads against 1-5 kb
+    divergent haplotypes, 30% low-quality reads): most leave the FP32 range."""
+    say("adjoint, precision-stress pairs (FP64 pass)")
+    full = wl.config3(pairs=2000)
+    idx = np.sort(np.random.default_rng(8).choice(full.num_pairs, 48, replace=False))
+    prob = full.select_pairs(idx)
+    lf = oracle.forward(prob)
+    say(f"  log10 L in [{lf.min():.1f}, {lf.max():.1f}], {int((lf < -64).sum())} of 48 below the FP32 range")
+    assert (lf < -64).sum() >= 24 and lf.min() > FP64_FLOOR_LOG10
+    u = np.random.default_rng(9).normal(size=prob.num_pairs)
+    ref, _ = oracle_grad(prob, u)
+    got, _ = gpu_grad(prob, u)
+    compare(got, ref, "precision stress")
+
+
+def test_adjoint_fp64_floor_gives_nan():
+    """A pair below the FP64 floor yields NaN gradients on its read's rows
+    when its upstream gradient is non-zero, and nothing when it is zero."""
+    say("adjoint, pair below the FP64 floor")
+    read_ok, read_far = "ACGTACGTAC" * 3, "ACGT" * 75   # 300 bases vs a 1-base haplotype
+    prob = wl.from_strings([([read_ok], ["ACGTACGTAC" * 4]), ([read_far], ["A"])], gcp_q=30)
+    lf = oracle.forward(prob)
+    assert lf[0] > -64 and lf[1] < -700, lf
+    got, _ = gpu_grad(prob, np.array([1.0, 1.0]))
+    assert np.all(np.isfinite(got[:30])) and np.all(np.isnan(got[30:]))
+    got0, _ = gpu_grad(prob, np.array([1.0, 0.0]))
+    ref, _ = oracle_grad(prob, np.array([1.0, 0.0]))
+    compare(got0, ref, "floor, u = 0")
 
 
 def test_adjoint_explicit_params():
