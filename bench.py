@@ -30,8 +30,38 @@ PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector peak
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes/clk x clock
 
 
+# HBM traffic of the FP32 sweep stage, from the committed rocprofv3 counter
+# summary; reported only while the forward kernel sources are the ones the
+# counters were taken on
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fwd32_hbm_traffic_mixed-2000regions.txt")
+FORWARD_SOURCES = ("paper_2411_11547_amd/csrc/ph_kernels.hip", "paper_2411_11547_amd/csrc/ph_device.h")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def forward_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in FORWARD_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name):
+    """(bytes per FP32 sweep stage, note) from the counter summary, or None
+    when it is missing, for another workload or for other kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("workload") != workload_name or kv.get("forward_sources_sha256") != forward_sources_sha256():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def workload(cfg: int):
@@ -212,7 +242,7 @@ def main():
     t32 = st_mean[1] * 1e-3
     achieved = FLOPS_PER_CELL * cells / t32 / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(prob.name),
             "kernel": "FP32 sweep stage (k_fwd32 over all length bins)",
             "kernel_ms": round(float(st_mean[1]), 4),
             "valu_slot_frac": round(VALU_PER_CELL * cells / t32 / PEAK_VALU_LANE_OPS, 4)}
