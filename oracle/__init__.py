@@ -54,6 +54,11 @@ def _load():
         lib.oracle_forward_pairs.restype = ctypes.c_int
         lib.oracle_forward_pairs.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, P, P, P,
                                              ctypes.c_int, ctypes.c_int, P]
+        lib.oracle_viterbi.restype = ctypes.c_double
+        lib.oracle_viterbi.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, ctypes.c_int]
+        lib.oracle_viterbi_pairs.restype = ctypes.c_int
+        lib.oracle_viterbi_pairs.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, P, P, P,
+                                             ctypes.c_int, ctypes.c_int, P]
         lib.oracle_backward_pairs.restype = ctypes.c_int
         lib.oracle_backward_pairs.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, P, P, P,
                                               ctypes.c_int, ctypes.c_int, P, P, P]
@@ -95,6 +100,15 @@ def forward_pair(read, hap, params, rescale=True, literal_n=False) -> float:
     read, hap, params = _u8(read), _u8(hap), _f64(params)
     assert params.shape == (len(read), NCH)
     return _load().oracle_forward(len(read), len(hap), _p(read), _p(hap), _p(params),
+                                  int(rescale), int(literal_n))
+
+
+def viterbi_pair(read, hap, params, rescale=True, literal_n=False) -> float:
+    """log10 of the most probable alignment path's probability (max-product
+    form of Eq. (1)-(3), result max_j of M(m,j), I(m,j))."""
+    read, hap, params = _u8(read), _u8(hap), _f64(params)
+    assert params.shape == (len(read), NCH)
+    return _load().oracle_viterbi(len(read), len(hap), _p(read), _p(hap), _p(params),
                                   int(rescale), int(literal_n))
 
 
@@ -152,6 +166,25 @@ def forward(problem, log10_params=None, pairs=None, literal_n=False, threads=Non
                                         _p(problem.hap_bases), _p(lp), int(literal_n), thr,
                                         _p(out))
     return (out, used) if return_threads else out
+
+
+def viterbi(problem, log10_params=None, pairs=None, literal_n=False, threads=None):
+    """log10 of the best path's probability for every pair (or the output
+    indices in `pairs`), in output order."""
+    r, h = problem.pair_index()
+    if pairs is not None:
+        pairs = np.asarray(pairs, dtype=np.int64)
+        r, h = r[pairs], h[pairs]
+    r = np.ascontiguousarray(r, np.int32); h = np.ascontiguousarray(h, np.int32)
+    out = np.empty(len(r), np.float64)
+    lp = None if log10_params is None else np.ascontiguousarray(log10_params, np.float32)
+    _load().oracle_viterbi_pairs(len(r), _p(r), _p(h), _p(problem.read_offset),
+                                 _p(problem.read_bases), _p(problem.base_qual),
+                                 _p(problem.ins_qual), _p(problem.del_qual),
+                                 _p(problem.gcp_qual), _p(problem.hap_offset),
+                                 _p(problem.hap_bases), _p(lp), int(literal_n),
+                                 threads or default_threads(), _p(out))
+    return out
 
 
 def backward(problem, log10_params=None, pairs=None, literal_n=False, threads=None):

@@ -70,6 +70,16 @@ def likelihood(read, hap, params, literal_n=False):
     return total, count
 
 
+def best_path(read, hap, params, literal_n=False):
+    """(probability of the most probable path, its states): the Viterbi
+    score by exhaustive search."""
+    best, trail = 0.0, None
+    for w, tr in enumerate_paths(read, hap, params, literal_n):
+        if w > best:
+            best, trail = w, tr
+    return best, trail
+
+
 def expected_uses(read, hap, params, literal_n=False):
     """Posterior expected number of uses of each parameter per read row:
     sum over paths of probability x (times the path uses theta_i) / L.

@@ -167,6 +167,81 @@ int oracle_forward_full(int m, int n, const uint8_t *r, const uint8_t *h, const 
 }
 
 /*
+ * Viterbi (max-product) form of the same model: every sum over predecessor
+ * states in Eq. (1)-(3) becomes a maximum and the result formula takes the
+ * largest M(m,j) or I(m,j) instead of their sum, which gives the probability
+ * of the single most probable alignment path:
+ *   V_M(i,j) = lam_ij * max(alpha_i V_M(i-1,j-1), beta_i V_I(i-1,j-1), beta_i V_D(i-1,j-1))
+ *   V_I(i,j) = max(delta_i V_M(i-1,j), eps_i V_I(i-1,j))
+ *   V_D(i,j) = max(zeta_i V_M(i,j-1), eps_i V_D(i,j-1))
+ * with the forward initialisation.  Rows are rescaled by powers of two as in
+ * the forward (exact, since max commutes with a positive scale).
+ */
+static double viterbi_matrices(int m, int n, const uint8_t *r, const uint8_t *h, const double *par,
+                               int rescale, int literal_n, double *M, double *I, double *D, int *e)
+{
+    const size_t W = (size_t)n + 1;
+    for (int j = 0; j <= n; j++) {
+        M[j] = 0.0;
+        I[j] = 0.0;
+        D[j] = 1.0 / n;
+    }
+    e[0] = 0;
+    for (int i = 1; i <= m; i++) {
+        const double *p = par + (size_t)(i - 1) * NCH;
+        double *Mi = M + i * W, *Ii = I + i * W, *Di = D + i * W;
+        const double *Mu = M + (i - 1) * W, *Iu = I + (i - 1) * W, *Du = D + (i - 1) * W;
+        Mi[0] = Ii[0] = Di[0] = 0.0;
+        for (int j = 1; j <= n; j++) {
+            double lam = is_match(r[i - 1], h[j - 1], literal_n) ? p[P_LMATCH] : p[P_LMIS];
+            double best = fmax(p[P_ALPHA] * Mu[j - 1], fmax(p[P_BETA] * Iu[j - 1], p[P_BETA] * Du[j - 1]));
+            Mi[j] = lam * best;
+            Ii[j] = fmax(p[P_DELTA] * Mu[j], p[P_EPS] * Iu[j]);
+            Di[j] = fmax(p[P_ZETA] * Mi[j - 1], p[P_EPS] * Di[j - 1]);
+        }
+        e[i] = e[i - 1];
+        if (rescale) {
+            double mx = 0.0;
+            for (int j = 0; j <= n; j++) {
+                if (Mi[j] > mx) mx = Mi[j];
+                if (Ii[j] > mx) mx = Ii[j];
+                if (Di[j] > mx) mx = Di[j];
+            }
+            if (mx > 0.0 && isfinite(mx)) {
+                int s;
+                frexp(mx, &s);
+                for (int j = 0; j <= n; j++) {
+                    Mi[j] = ldexp(Mi[j], -s);
+                    Ii[j] = ldexp(Ii[j], -s);
+                    Di[j] = ldexp(Di[j], -s);
+                }
+                e[i] += s;
+            }
+        }
+    }
+    double best = 0.0;
+    const double *Mm = M + (size_t)m * W, *Im = I + (size_t)m * W;
+    for (int j = 1; j <= n; j++) best = fmax(best, fmax(Mm[j], Im[j]));
+    return best;
+}
+
+/* log10 of the best path's probability; -inf if no path has weight. */
+double oracle_viterbi(int m, int n, const uint8_t *r, const uint8_t *h, const double *par, int rescale,
+                      int literal_n)
+{
+    if (m < 1 || n < 1) return NAN;
+    size_t cells = (size_t)(m + 1) * (n + 1);
+    double *buf = malloc(3 * cells * sizeof(double));
+    int *e = malloc((size_t)(m + 1) * sizeof(int));
+    if (!buf || !e) { free(buf); free(e); return NAN; }
+    double s = viterbi_matrices(m, n, r, h, par, rescale, literal_n, buf, buf + cells, buf + 2 * cells, e);
+    double out = to_log10(s, e[m]);
+    free(buf);
+    free(e);
+    return out;
+}
+
+/*
  * Backward (adjoint) pass and gradients of one pair.
  *
  * B_X(i,j) = dL/dX(i,j).  L takes M(m,j) and I(m,j) with weight one, so
@@ -312,6 +387,7 @@ typedef struct {
     const uint8_t *read_bases, *bq, *iq, *dq, *gq, *hap_bases;
     const float *log10_par;
     int literal_n;
+    int viterbi;       /* 1: max-product score instead of the forward likelihood */
     double *out;       /* forward: log10 L per pair */
     double *grad_ext;  /* backward: [sum over pairs of m x 8] or NULL */
     const int64_t *grad_offset; /* per pair, row offset into grad_ext */
@@ -339,6 +415,9 @@ static void *batch_worker(void *arg)
                                 jb->grad_ext + jb->grad_offset[k] * NEXT, &lf, &lb) != 0)
                 lf = NAN;
             jb->out[k] = lf;
+        } else if (jb->viterbi) {
+            jb->out[k] = oracle_viterbi(m, n, jb->read_bases + ro, jb->hap_bases + ho, par, 1,
+                                        jb->literal_n);
         } else {
             jb->out[k] = oracle_forward(m, n, jb->read_bases + ro, jb->hap_bases + ho, par, 1,
                                         jb->literal_n);
@@ -383,6 +462,30 @@ int oracle_forward_pairs(int64_t num_pairs, const int32_t *pair_read, const int3
     jb.hap_bases = hap_bases;
     jb.log10_par = log10_par;
     jb.literal_n = literal_n;
+    jb.out = out_log10;
+    return run_pool(&jb, threads);
+}
+
+/* Viterbi scores over an explicit pair list; returns the number of threads used. */
+int oracle_viterbi_pairs(int64_t num_pairs, const int32_t *pair_read, const int32_t *pair_hap,
+                         const int64_t *read_offset, const uint8_t *read_bases,
+                         const uint8_t *bq, const uint8_t *iq, const uint8_t *dq,
+                         const uint8_t *gq, const int64_t *hap_offset,
+                         const uint8_t *hap_bases, const float *log10_par, int literal_n,
+                         int threads, double *out_log10)
+{
+    batch_job jb = {0};
+    jb.num_pairs = num_pairs;
+    jb.pair_read = pair_read;
+    jb.pair_hap = pair_hap;
+    jb.read_offset = read_offset;
+    jb.hap_offset = hap_offset;
+    jb.read_bases = read_bases;
+    jb.bq = bq; jb.iq = iq; jb.dq = dq; jb.gq = gq;
+    jb.hap_bases = hap_bases;
+    jb.log10_par = log10_par;
+    jb.literal_n = literal_n;
+    jb.viterbi = 1;
     jb.out = out_log10;
     return run_pool(&jb, threads);
 }

@@ -293,3 +293,67 @@ def test_output_order_and_selection():
     assert list(r) == [0, 0, 0, 1, 1, 1, 2] and list(h) == [0, 1, 2, 0, 1, 2, 3]
     sub = prob.select_pairs([4, 6])
     assert np.allclose(oracle.forward(sub), oracle.forward(prob)[[4, 6]], atol=0)
+
+
+# --- Viterbi (max-product) form --------------------------------------------------------
+@pytest.mark.parametrize("literal_n", [False, True])
+def test_viterbi_equals_bruteforce_best_path(literal_n):
+    """The max-product DP equals the largest single-path probability found
+    by enumerating every path; and V <= L <= V x (number of paths)."""
+    rng = np.random.default_rng(31 + literal_n)
+    for trial in range(60):
+        m = int(rng.integers(1, 6))
+        n = int(rng.integers(1, 7))
+        r = rng.integers(0, 5, m).astype(np.uint8)
+        h = rng.integers(0, 5, n).astype(np.uint8)
+        p = random_params(rng, m, normalised=bool(trial % 2))
+        best, trail = bruteforce.best_path(r, h, p, literal_n)
+        L, count = bruteforce.likelihood(r, h, p, literal_n)
+        v = oracle.viterbi_pair(r, h, p, literal_n=literal_n)
+        assert 10 ** v == pytest.approx(best, rel=1e-12), (m, n, trial)
+        assert best <= L * (1 + 1e-12) and L <= best * count * (1 + 1e-12)
+
+
+def test_viterbi_single_path_equals_forward():
+    """A 1x1 pair has exactly one path, so its Viterbi score is L."""
+    rng = np.random.default_rng(32)
+    for _ in range(10):
+        p = random_params(rng, 1)
+        r, h = rng.integers(0, 5, 1).astype(np.uint8), rng.integers(0, 5, 1).astype(np.uint8)
+        assert bruteforce.likelihood(r, h, p)[1] == 1
+        assert oracle.viterbi_pair(r, h, p) == pytest.approx(oracle.forward_pair(r, h, p), abs=1e-14)
+
+
+def test_viterbi_ungapped_max_scan_150x300():
+    """delta = zeta = 0, alpha = 1: the best path is the best diagonal,
+    (beta_1 / n) x max over offsets of the product of emissions."""
+    rng = np.random.default_rng(33)
+    m, n = 150, 300
+    r = rng.integers(0, 4, m).astype(np.uint8)
+    h = rng.integers(0, 4, n).astype(np.uint8)
+    h[70:70 + m] = r
+    Q = 10 ** -rng.uniform(1, 4, m)
+    p = np.stack([np.ones(m), np.full(m, 0.9), np.zeros(m), np.full(m, 0.1), np.zeros(m), 1 - Q, Q / 3], 1)
+    logs = [np.sum(np.log10(np.where(r == h[j0:j0 + m], p[:, 5], p[:, 6]))) for j0 in range(n - m + 1)]
+    want = math.log10(p[0, 1] / n) + max(logs)
+    assert oracle.viterbi_pair(r, h, p) == pytest.approx(want, abs=1e-11)
+
+
+def test_viterbi_rescaling_and_batch_driver():
+    """Row rescaling leaves in-range scores unchanged, and the batch driver
+    equals the single-pair calls (Phred and explicit parameters)."""
+    prob = wl.config0()
+    r_idx, h_idx = prob.pair_index()
+    got = oracle.viterbi(prob)
+    lg = np.log10(oracle.params_from_phred(prob.base_qual, prob.ins_qual, prob.del_qual,
+                                           prob.gcp_qual)).astype(np.float32)
+    got_lg = oracle.viterbi(prob, log10_params=lg)
+    for k in range(prob.num_pairs):
+        rd = prob.read(r_idx[k])
+        p = oracle.params_from_phred(rd[1], rd[2], rd[3], rd[4])
+        v0 = oracle.viterbi_pair(rd[0], prob.hap(h_idx[k]), p, rescale=False)
+        # the rescaled score differs from the plain one only in the final log10 rounding
+        assert oracle.viterbi_pair(rd[0], prob.hap(h_idx[k]), p) == pytest.approx(v0, abs=1e-12)
+        assert got[k] == oracle.viterbi_pair(rd[0], prob.hap(h_idx[k]), p)
+        assert got_lg[k] == pytest.approx(v0, abs=1e-6)
+    assert np.all(got <= oracle.forward(prob) + 1e-12)
