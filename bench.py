@@ -69,6 +69,21 @@ def workload(cfg: int):
     return wl.make(cfg)
 
 
+def time_forward_fn(fn, plan, steps, warmup):
+    """Like time_forward for any plan call (the Viterbi score)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stages = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+        stages.append(plan.stage_ms())
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, np.array(stages)
+
+
 def time_forward(plan, dev, steps, warmup, stage=True):
     import torch
     for _ in range(warmup):
@@ -88,13 +103,41 @@ def time_forward(plan, dev, steps, warmup, stage=True):
 ADJ_FLOPS_PER_CELL = 37  # 11 recompute + 11 adjoint + 15 gradient accumulation (FP32)
 
 
-def time_adjoint(steps):
-    """Backward pass (checkpointed forward + reverse sweep + gradients) on
-    the adjoint workload: 10,000 pairs, 150 bp reads x 200-600 bp haplotypes."""
+def time_pipeline(prob, subsets=8, steps=2):
+    """Host-input streaming forward (the paper's workflow, Section III-A):
+    pinned host arrays in, scores on the host out, H2D of the next subset
+    overlapped with the current subset's compute.  Not the headline value:
+    it includes the PCIe transfers."""
+    from paper_2411_11547_amd import binding
+    pipe = binding.Pipeline(prob, max_subset_cells=prob.total_cells // subsets + 1)
+    pipe.forward()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pipe.forward()
+    sec = (time.perf_counter() - t0) / steps
+    ev_ms = pipe.ms()
+    nsub = pipe.num_subsets
+    pipe.close()
+    h2d = int(prob.read_offset[-1]) * 5 + int(prob.hap_offset[-1])
+    log(f"host-input pipeline: {sec * 1e3:.2f} ms/call over {nsub} subsets, "
+        f"{prob.total_cells / sec / 1e9:.1f} GCUPS")
+    return {"gcups": round(prob.total_cells / sec / 1e9, 2), "ms_per_call": round(sec * 1e3, 3),
+            "event_ms": round(ev_ms, 3), "subsets": nsub, "pinned": True,
+            "h2d_bytes": h2d, "d2h_bytes": prob.num_pairs * 9,
+            "includes": "H2D of bases and qualities, binning, FP32 sweeps, FP64 rescue, D2H of scores"}
+
+
+def time_adjoint(steps, prob=None, dev=None):
+    """Backward pass (checkpointed forward + reverse sweep + gradients, FP64
+    for pairs outside the FP32 range), upstream gradient 1 for every pair:
+    on `prob` (the mixed batch) or by default on the adjoint workload
+    (10,000 pairs, 150 bp reads x 200-600 bp haplotypes)."""
     import torch
     from paper_2411_11547_amd import binding, workloads as wl
-    prob = wl.config4()
-    dev = binding.DeviceProblem(prob)
+    if prob is None:
+        prob = wl.config4()
+    if dev is None:
+        dev = binding.DeviceProblem(prob)
     plan = binding.Plan(prob, keep_checkpoints=True)
     u = torch.ones(prob.num_pairs, dtype=torch.float64, device="cuda")
     grad = torch.empty((int(prob.read_offset[-1]), 7), dtype=torch.float32, device="cuda")
@@ -180,6 +223,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune-table", default=None)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-e2e", action="store_true", help="skip the host-input pipeline timing")
     ap.add_argument("--launch", choices=["bins", "single"], default="bins",
                     help="FP32 sweep as one launch per length bin or one persistent launch")
     ap.add_argument("--no-ab", action="store_true", help="skip timing the other launch mode")
@@ -219,6 +263,14 @@ def main():
     st_mean = stages.mean(axis=0)
     log(f"binned: {sec * 1e3:.2f} ms/step, {gcups:.1f} GCUPS, stages(ms) bin={st_mean[0]:.3f} "
         f"fp32={st_mean[1]:.3f} fp64={st_mean[2]:.3f}, rescued {rescued}")
+    # the Viterbi score (max-product sweep) on the same plan and batch
+    vsec, vst = time_forward_fn(lambda: plan.viterbi(dev), plan, 3, 1)
+    viterbi = {"gcups": round(cells / vsec / 1e9, 2), "ms_per_step": round(vsec * 1e3, 3),
+               "stage_ms": {"binning": round(float(vst.mean(axis=0)[0]), 4),
+                            "fp32_sweep": round(float(vst.mean(axis=0)[1]), 4),
+                            "fp64_rescue": round(float(vst.mean(axis=0)[2]), 4)},
+               "fp32_valu_per_cell": 10}
+    log(f"viterbi: {vsec * 1e3:.2f} ms/step, {viterbi['gcups']:.1f} GCUPS")
     plan.close()
 
     other = None
@@ -248,6 +300,8 @@ def main():
             "valu_slot_frac": round(VALU_PER_CELL * cells / t32 / PEAK_VALU_LANE_OPS, 4)}
 
     adj = None if args.no_adjoint else time_adjoint(args.adjoint_steps)
+    adj_mixed = None if args.no_adjoint else time_adjoint(max(1, args.adjoint_steps // 2), prob, dev)
+    e2e = None if args.no_e2e else time_pipeline(prob)
 
     cpu = None if args.no_cpu else cpu_baseline(prob)
     if cpu:
@@ -267,7 +321,10 @@ def main():
            "stage_ms": {"binning": round(float(st_mean[0]), 4), "fp32_sweep": round(float(st_mean[1]), 4),
                         "fp64_rescue": round(float(st_mean[2]), 4)},
            "adjoint_gcups": None if adj is None else adj["gcups"],
+           "viterbi": viterbi,
            "adjoint": adj,
+           "adjoint_mixed": adj_mixed,
+           "end_to_end_host_input": e2e,
            "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     if args.copy_probe_mib:

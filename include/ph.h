@@ -33,6 +33,7 @@
 #ifndef PH_H
 #define PH_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -42,7 +43,7 @@ extern "C" {
 typedef enum {
     PH_OK = 0,
     PH_ERR_INVALID = -1,       /* bad argument: NULL pointer, empty read or haplotype, bad code */
-    PH_ERR_UNSUPPORTED = -2,   /* read longer than the longest compiled kernel configuration */
+    PH_ERR_UNSUPPORTED = -2,   /* read longer than 65535 bases (forward) or 319 (adjoint) */
     PH_ERR_NOMEM = -3,         /* device or host allocation failed */
     PH_ERR_HIP = -4,           /* a HIP runtime call failed; see ph_last_error() */
     PH_ERR_PLAN_MISMATCH = -5, /* the problem does not have the shape the plan was built for */
@@ -96,7 +97,9 @@ typedef struct {
      * corresponds to log10 L of about -64.1.  <= 0 selects the default;
      * +inf sends every pair to the FP64 sweep. */
     double rescue_threshold;
-    int use_graph;         /* 1: capture the launch sequence once and replay it */
+    int use_graph;         /* 1: capture the launch sequence of ph_forward_batch (three
+                              stage graphs) and of ph_backward_batch once per set of
+                              buffers and replay it */
     int plain;             /* 1: one FP32 kernel sized for the longest read, pairs
                               in output order, no binning, no rescue (baseline) */
     int force_p;           /* 0 = tuned; else lanes per pair (16, 32 or 64) for every bin */
@@ -116,9 +119,12 @@ void ph_plan_opts_default(ph_plan_opts *opts);
 
 /* Build a plan for problems of the given shape (HOST arrays, read once).
  * Validates the shape: batch ranges inside the read/haplotype counts, every
- * read and haplotype non-empty (PH_ERR_INVALID), every read within the
- * compiled range (PH_ERR_UNSUPPORTED); then sizes and allocates device
- * scratch on the current device.  *out receives the plan. */
+ * read and haplotype non-empty (PH_ERR_INVALID), every read at most 65535
+ * bases (PH_ERR_UNSUPPORTED; plain mode: 1023); then sizes and allocates
+ * device scratch on the current device.  Reads of up to 1023 bases are
+ * binned by length; longer reads are swept in windows of 1024 rows whose
+ * boundary rows (3 values per haplotype column) live in plan scratch.
+ * *out receives the plan. */
 ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts, ph_plan **out);
 
 /* Number of pairs P = sum_q |R_q| |H_q| and real cells sum_pairs m*n. */
@@ -136,20 +142,30 @@ ph_status ph_forward_batch(ph_plan *plan, const ph_problem *problem,
                            const float *log10_params, double *out_log10L,
                            uint8_t *out_status, void *stream);
 
+/* Viterbi score (the max-product form of Eq. (1)-(3): every sum over
+ * predecessor states a maximum, and the largest M(m,j) or I(m,j) instead of
+ * their sum): out_log10V[P] receives log10 of the probability of each pair's
+ * most probable alignment path, with the same binning, FP64 rescue, status
+ * codes, arguments and output order as ph_forward_batch.  Not available in
+ * plain mode (PH_ERR_UNSUPPORTED). */
+ph_status ph_viterbi_batch(ph_plan *plan, const ph_problem *problem,
+                           const float *log10_params, double *out_log10V,
+                           uint8_t *out_status, void *stream);
+
 /* Adjoint pass: grad_params[read_offset[num_reads]][7] (device, float)
  * receives d(sum_p u_p log10 L_p)/d log10 theta for the seven parameters of
  * every read base, u = grad_log10L[P] (device, double).  The derivative of
  * Eq. (1)-(4) run backwards; d log10 L / d log10 theta is the posterior
  * expected number of uses of theta.  The call runs its own checkpointed FP32
- * forward (row checkpoints at every lane boundary, lane-state checkpoints
- * every 4 columns) and then the reverse sweep, so it needs no preceding
- * forward call.  Pairs whose scaled FP32 sum falls below the plan's rescue
- * threshold (or overflows) are redone in FP64 (Section III-C's two-level
- * precision), and only pairs below the FP64 floor (log10 L < about -608) get
- * NaN gradients; pairs with u_p = 0 contribute nothing and are skipped.  The
- * gradient buffer is overwritten.  Reads longer than 319 bases give
- * PH_ERR_UNSUPPORTED.  Sums over pairs sharing a read use float atomics, so
- * the last bits of a gradient may depend on completion order. */
+ * forward (every lane's state, i.e. every K-th row, every 4 columns) and
+ * then the reverse sweep, so it needs no preceding forward call.  Pairs
+ * whose scaled FP32 sum falls below the plan's rescue threshold (or
+ * overflows) are redone in FP64, as in the forward; only pairs below the
+ * FP64 floor (log10 L < about -608) get NaN gradients, and pairs with
+ * u_p = 0 contribute nothing.  The gradient buffer is overwritten.  Reads
+ * longer than 319 bases give PH_ERR_UNSUPPORTED.  Sums over pairs sharing a
+ * read use float atomics, so the last bits of a gradient may depend on
+ * completion order. */
 ph_status ph_backward_batch(ph_plan *plan, const ph_problem *problem,
                             const float *log10_params, const double *grad_log10L,
                             float *grad_params, void *stream);
@@ -170,6 +186,49 @@ ph_status ph_plan_stage_ms(ph_plan *plan, float ms[4]);
 ph_status ph_plan_rescued(ph_plan *plan, int64_t *count);
 
 void ph_plan_destroy(ph_plan *plan);
+
+/* ---- Streaming forward over host-resident batches ------------------------
+ * The workflow of Section III-A: the batches are cut into subsets of whole
+ * batches, subset k+1 is copied to the GPU while subset k is binned and
+ * computed (one plan per subset), and each subset's scores are copied back as
+ * soon as it finishes.  Copies overlap compute only when the host arrays are
+ * pinned (allocate them with ph_host_alloc); pageable arrays work but their
+ * copies are staged by the runtime. */
+typedef struct {
+    int64_t max_subset_cells; /* cells (sum of m*n) per subset; a larger batch forms a
+                                 subset of its own; <= 0 selects 2e10 */
+    ph_plan_opts plan;        /* options of every subset's plan */
+} ph_pipeline_opts;
+
+typedef struct ph_pipeline ph_pipeline; /* opaque: subset plans, two device buffer sets, streams */
+
+void ph_pipeline_opts_default(ph_pipeline_opts *opts);
+
+/* Partition the shape (HOST arrays, read once) into subsets and create their
+ * plans and the device buffers on the current device.  Errors as
+ * ph_plan_create. */
+ph_status ph_pipeline_create(const ph_shape *shape, const ph_pipeline_opts *opts, ph_pipeline **out);
+
+ph_status ph_pipeline_info(const ph_pipeline *pipe, int32_t *num_subsets, int64_t *num_pairs,
+                           int64_t *num_cells);
+
+/* Forward pass of a problem held in HOST memory (every ph_problem array is a
+ * host pointer; the CSR arrays must match the shape).  out_log10L[P] and
+ * out_status[P] (may be NULL) are HOST arrays in the order of
+ * ph_forward_batch.  Synchronous: returns when the scores are on the host. */
+ph_status ph_pipeline_forward(ph_pipeline *pipe, const ph_problem *host_problem, double *out_log10L,
+                              uint8_t *out_status);
+
+/* Milliseconds from the first host-to-device copy to the last device-to-host
+ * copy of the most recent ph_pipeline_forward, from HIP events. */
+ph_status ph_pipeline_ms(ph_pipeline *pipe, float *ms);
+
+void ph_pipeline_destroy(ph_pipeline *pipe);
+
+/* Pinned host memory for pipeline inputs and outputs (hipHostMalloc); NULL on
+ * failure. */
+void *ph_host_alloc(size_t bytes);
+void ph_host_free(void *ptr);
 
 /* Message of the calling thread's most recent failure ("" if none). */
 const char *ph_last_error(void);

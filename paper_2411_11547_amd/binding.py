@@ -23,9 +23,11 @@ STATUS_NAMES = {0: "PH_OK", -1: "PH_ERR_INVALID", -2: "PH_ERR_UNSUPPORTED", -3: 
                 -4: "PH_ERR_HIP", -5: "PH_ERR_PLAN_MISMATCH", -6: "PH_ERR_STATE"}
 PAIR_FP32, PAIR_FP64, PAIR_FP64_FLOOR, PAIR_FP32_UNRESCUED = 0, 1, 2, 3
 
-EXPORTS = ("ph_plan_opts_default", "ph_plan_create", "ph_plan_info", "ph_forward_batch",
+EXPORTS = ("ph_plan_opts_default", "ph_plan_create", "ph_plan_info", "ph_forward_batch", "ph_viterbi_batch",
            "ph_backward_batch", "ph_validate", "ph_plan_stage_ms", "ph_plan_rescued",
-           "ph_plan_destroy", "ph_last_error", "ph_version")
+           "ph_plan_destroy", "ph_last_error", "ph_version",
+           "ph_pipeline_opts_default", "ph_pipeline_create", "ph_pipeline_info", "ph_pipeline_forward",
+           "ph_pipeline_ms", "ph_pipeline_destroy", "ph_host_alloc", "ph_host_free")
 
 _p = ctypes.c_void_p
 
@@ -48,6 +50,10 @@ class PhPlanOpts(ctypes.Structure):
                 ("plain", ctypes.c_int), ("force_p", ctypes.c_int),
                 ("keep_checkpoints", ctypes.c_int), ("tune_table_path", ctypes.c_char_p),
                 ("single_launch", ctypes.c_int)]
+
+
+class PhPipelineOpts(ctypes.Structure):
+    _fields_ = [("max_subset_cells", ctypes.c_int64), ("plan", PhPlanOpts)]
 
 
 class PHError(RuntimeError):
@@ -74,6 +80,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ph_plan_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.ph_forward_batch.argtypes = [P, ctypes.POINTER(PhProblem), P, P, P, P]
+    lib.ph_viterbi_batch.argtypes = [P, ctypes.POINTER(PhProblem), P, P, P, P]
     lib.ph_backward_batch.argtypes = [P, ctypes.POINTER(PhProblem), P, P, P, P]
     lib.ph_validate.argtypes = [P, ctypes.POINTER(PhProblem), P]
     lib.ph_plan_stage_ms.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
@@ -84,8 +91,23 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ph_last_error.argtypes = []
     lib.ph_version.restype = ctypes.c_char_p
     lib.ph_version.argtypes = []
-    for name in ("ph_plan_create", "ph_plan_info", "ph_forward_batch", "ph_backward_batch",
-                 "ph_validate", "ph_plan_stage_ms", "ph_plan_rescued"):
+    lib.ph_pipeline_opts_default.argtypes = [ctypes.POINTER(PhPipelineOpts)]
+    lib.ph_pipeline_opts_default.restype = None
+    lib.ph_pipeline_create.argtypes = [ctypes.POINTER(PhShape), ctypes.POINTER(PhPipelineOpts),
+                                       ctypes.POINTER(P)]
+    lib.ph_pipeline_info.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int64)]
+    lib.ph_pipeline_forward.argtypes = [P, ctypes.POINTER(PhProblem), P, P]
+    lib.ph_pipeline_ms.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
+    lib.ph_pipeline_destroy.argtypes = [P]
+    lib.ph_pipeline_destroy.restype = None
+    lib.ph_host_alloc.argtypes = [ctypes.c_size_t]
+    lib.ph_host_alloc.restype = P
+    lib.ph_host_free.argtypes = [P]
+    lib.ph_host_free.restype = None
+    for name in ("ph_plan_create", "ph_plan_info", "ph_forward_batch", "ph_viterbi_batch", "ph_backward_batch",
+                 "ph_validate", "ph_plan_stage_ms", "ph_plan_rescued", "ph_pipeline_create",
+                 "ph_pipeline_info", "ph_pipeline_forward", "ph_pipeline_ms"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -169,6 +191,10 @@ def ph_forward_batch(plan, problem: PhProblem, log10_params, out_log10L, out_sta
     _check(load().ph_forward_batch(plan, ctypes.byref(problem), log10_params, out_log10L, out_status, stream))
 
 
+def ph_viterbi_batch(plan, problem: PhProblem, log10_params, out_log10V, out_status, stream):
+    _check(load().ph_viterbi_batch(plan, ctypes.byref(problem), log10_params, out_log10V, out_status, stream))
+
+
 def ph_backward_batch(plan, problem: PhProblem, log10_params, grad_log10L, grad_params, stream):
     _check(load().ph_backward_batch(plan, ctypes.byref(problem), log10_params, grad_log10L, grad_params, stream))
 
@@ -195,6 +221,72 @@ def ph_plan_destroy(plan):
 
 def ph_version() -> str:
     return load().ph_version().decode()
+
+
+def ph_pipeline_opts_default() -> PhPipelineOpts:
+    o = PhPipelineOpts()
+    load().ph_pipeline_opts_default(ctypes.byref(o))
+    return o
+
+
+def ph_pipeline_create(shape: PhShape, opts: PhPipelineOpts) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(load().ph_pipeline_create(ctypes.byref(shape), ctypes.byref(opts), ctypes.byref(h)))
+    return h
+
+
+def ph_pipeline_info(pipe):
+    n, P, C = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().ph_pipeline_info(pipe, ctypes.byref(n), ctypes.byref(P), ctypes.byref(C)))
+    return n.value, P.value, C.value
+
+
+def ph_pipeline_forward(pipe, host_problem: PhProblem, out_log10L, out_status):
+    _check(load().ph_pipeline_forward(pipe, ctypes.byref(host_problem), out_log10L, out_status))
+
+
+def ph_pipeline_ms(pipe) -> float:
+    ms = ctypes.c_float()
+    _check(load().ph_pipeline_ms(pipe, ctypes.byref(ms)))
+    return ms.value
+
+
+def ph_pipeline_destroy(pipe):
+    load().ph_pipeline_destroy(pipe)
+
+
+def ph_host_alloc(nbytes: int) -> int:
+    p = load().ph_host_alloc(max(int(nbytes), 1))
+    if not p:
+        raise PHError(-3, "ph_host_alloc failed")
+    return p
+
+
+def ph_host_free(ptr):
+    load().ph_host_free(ptr)
+
+
+class PinnedArray:
+    """A numpy view of pinned host memory from ph_host_alloc."""
+
+    def __init__(self, arr):
+        arr = np.ascontiguousarray(arr)
+        self.ptr = ph_host_alloc(arr.nbytes)
+        buf = (ctypes.c_uint8 * max(arr.nbytes, 1)).from_address(self.ptr)
+        self.a = np.frombuffer(buf, dtype=arr.dtype, count=arr.size).reshape(arr.shape)
+        self.a[...] = arr
+
+    def close(self):
+        if self.ptr:
+            self.a = None
+            ph_host_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # --- convenience wrapper --------------------------------------------------------
@@ -233,6 +325,18 @@ class Plan:
                          ctypes.c_void_p(status.data_ptr()), stream or current_stream())
         return out[:self.num_pairs], status[:self.num_pairs]
 
+    def viterbi(self, dev: DeviceProblem, log10_params=None, out=None, status=None, stream=None):
+        """log10 of each pair's best-path probability (ph_viterbi_batch)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(max(self.num_pairs, 1), dtype=torch.float64, device="cuda")
+        if status is None:
+            status = torch.empty(max(self.num_pairs, 1), dtype=torch.uint8, device="cuda")
+        lp = None if log10_params is None else ctypes.c_void_p(log10_params.data_ptr())
+        ph_viterbi_batch(self.handle, dev.c, lp, ctypes.c_void_p(out.data_ptr()),
+                         ctypes.c_void_p(status.data_ptr()), stream or current_stream())
+        return out[:self.num_pairs], status[:self.num_pairs]
+
     def backward(self, dev: DeviceProblem, grad_log10L, log10_params=None, grad_params=None, stream=None):
         """Gradient of sum_p grad_log10L[p] * log10 L_p w.r.t. the log10
         parameters of every read base: float32 [sum m, 7]."""
@@ -260,6 +364,62 @@ class Plan:
         if getattr(self, "handle", None):
             ph_plan_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pipeline:
+    """Streaming forward over a host-resident problem (ph_pipeline_*): the
+    problem's arrays are copied once into pinned host memory here, the calls
+    then move them subset by subset."""
+
+    DATA = ("read_bases", "base_qual", "ins_qual", "del_qual", "gcp_qual", "hap_bases")
+
+    def __init__(self, problem, max_subset_cells=0, pinned=True, **plan_kw):
+        opts = ph_pipeline_opts_default()
+        opts.max_subset_cells = int(max_subset_cells)
+        for k, v in plan_kw.items():
+            setattr(opts.plan, k, v)
+        shape, self._keep = shape_of(problem)
+        self.handle = ph_pipeline_create(shape, opts)
+        self.num_subsets, self.num_pairs, self.num_cells = ph_pipeline_info(self.handle)
+        self._host = {}
+        for f in self.DATA:
+            arr = np.ascontiguousarray(getattr(problem, f))
+            self._host[f] = PinnedArray(arr) if pinned else arr
+        self.out = PinnedArray(np.zeros(max(self.num_pairs, 1))) if pinned else np.zeros(max(self.num_pairs, 1))
+        self.status = PinnedArray(np.zeros(max(self.num_pairs, 1), np.uint8)) if pinned else \
+            np.zeros(max(self.num_pairs, 1), np.uint8)
+        k = self._keep
+        hp = lambda f: ctypes.c_void_p((self._host[f].a if pinned else self._host[f]).ctypes.data)
+        self.c = PhProblem(problem.num_batches, _np_ptr(k[0]), _np_ptr(k[1]), problem.num_reads, _np_ptr(k[2]),
+                           hp("read_bases"), hp("base_qual"), hp("ins_qual"), hp("del_qual"), hp("gcp_qual"),
+                           problem.num_haps, _np_ptr(k[3]), hp("hap_bases"))
+        self.pinned = pinned
+
+    def _arr(self, x):
+        return x.a if self.pinned else x
+
+    def forward(self):
+        """Scores (float64) and statuses (uint8) of every pair, host arrays."""
+        out, st = self._arr(self.out), self._arr(self.status)
+        ph_pipeline_forward(self.handle, self.c, ctypes.c_void_p(out.ctypes.data), ctypes.c_void_p(st.ctypes.data))
+        return out[:self.num_pairs].copy(), st[:self.num_pairs].copy()
+
+    def ms(self) -> float:
+        return ph_pipeline_ms(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ph_pipeline_destroy(self.handle)
+            self.handle = None
+        if getattr(self, "pinned", False):
+            for v in list(self._host.values()) + [self.out, self.status]:
+                v.close()
 
     def __del__(self):
         try:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpairhmm.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["ph_kernels.hip", "ph_adjoint.hip", "ph_api.cpp"]
+SOURCES = ["ph_kernels.hip", "ph_adjoint.hip", "ph_api.cpp", "ph_pipeline.cpp"]
 ARCH = os.environ.get("PH_OFFLOAD_ARCH", "gfx950")
 
 

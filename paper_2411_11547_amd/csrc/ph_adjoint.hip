@@ -16,22 +16,24 @@
 // value, divided by L.
 //
 // Layout: the lane structure of the forward sweep (P lanes per pair, K rows
-// per lane).  Memory is bounded by checkpoints:
-//  * row checkpoints: every lane stores the values of the row above its
-//    first row as it receives them (one row every K rows, every column);
-//  * column checkpoints: every CB steps each lane stores its K-row state.
-// The backward walks the forward steps in reverse, CB at a time: each lane
-// reloads its state at the start of the block, recomputes the block's CB
-// columns in registers from the stored row above (no lane exchange is needed
-// for that), then runs the reverse wavefront over them.  All lanes sit at
-// the same forward step (each on its own column), so the block structure is
-// the same in every lane.
+// per lane, lane t at column j = s - t + 1 of step s).  Memory is bounded by
+// checkpoints: every CB steps each lane stores its K-row state and the three
+// diagonal values it holds from the lane above, 3K + 3 values per lane.  The
+// backward walks the blocks of CB steps in reverse: the wave reloads a
+// block's checkpoint, recomputes the block's CB steps as a wavefront (the
+// same lane exchange as the forward, so nothing else needs storing), keeps
+// them in registers and runs the reverse wavefront over them.
 //
-// Precision (the two-level scheme of Section III-C carried over to the
-// adjoint): an FP32 pass handles every pair; a pair whose scaled FP32 sum
-// leaves the FP32 range is queued by read-length class and redone by an FP64
-// pass (64 lanes per pair, one pair at a time per workgroup, checkpoints in a
-// fixed per-workgroup slice of an FP64 workspace).
+// One persistent workgroup per slot takes a tile (G = 64/P pairs of one
+// (P, K) configuration), runs the checkpointed forward into its own slice of
+// the workspace and then the reverse sweep; the slice is read back soon after
+// it is written, in reverse order, and waves in the forward phase (stores)
+// overlap waves in the reverse phase (arithmetic).
+//
+// Precision (the forward's FP32 sweep with FP64 recomputation, carried over
+// to the adjoint): an FP32 pass handles every pair; a pair whose scaled FP32
+// sum leaves the FP32 range is queued by read-length class and redone by an
+// FP64 pass (64 lanes per pair, one pair at a time per workgroup).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -204,49 +206,44 @@ __device__ __forceinline__ void adj_cell_step(const T (&mo)[K], const T (&io)[K]
     }
 }
 
-// Checkpointed forward.  Workspace of one pair: [S+1][3][P] row checkpoints
-// (slot s+1 = the row above as received at step s, slot 0 = the initial
-// diagonal), then [S/CB][3][K][P] column checkpoints (lane state before
-// steps 0, CB, 2 CB, ...).  Returns, in lane P-1, the scaled row-m sum.
+// Checkpointed forward of the wave's pairs.  ck: the workgroup's slice,
+// [S/CB][3K+3][64] values (lane state M, I, D and the diagonal md, id, dd
+// before steps 0, CB, 2 CB, ...).  Returns, in lane P-1 of each group, the
+// scaled row-m sum.
+template <typename T, int K>
+struct AdjCk {
+    static constexpr int V = 3 * K + 3;  // values per lane per checkpoint
+};
+
 template <typename T, int P, int K, int CB>
-__device__ __forceinline__ double adj_forward(const AdjPair<T, P, K> &pr, T *bnd, T *ck, bool wr)
+__device__ __forceinline__ double adj_forward(const AdjPair<T, P, K> &pr, T *ck)
 {
+    constexpr int V = AdjCk<T, K>::V;
     const int t = pr.t, S = pr.S;
     const T edge = (t == 0) ? (T)(ldexp(1.0, AdjRange<T>::kFwd) / (double)pr.n) : (T)0;  // D(0, j) = 1/n, scaled
     T M[K], I[K], D[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) M[r] = I[r] = D[r] = (T)0;
     T md = 0, id = 0, dd = edge;
-    if (wr) {
-        bnd[0 * P + t] = (T)0;
-        bnd[1 * P + t] = (T)0;
-        bnd[2 * P + t] = dd;
-    }
     double acc = 0.0;
     for (int s0 = 0; s0 < S; s0 += CB) {
-        if (wr) {
-            T *cq = ck + (int64_t)(s0 / CB) * 3 * K * P + t;
+        T *cq = ck + (int64_t)(s0 / CB) * V * 64 + pr.lane;
 #pragma unroll
-            for (int r = 0; r < K; ++r) {
-                cq[(0 * K + r) * P] = M[r];
-                cq[(1 * K + r) * P] = I[r];
-                cq[(2 * K + r) * P] = D[r];
-            }
+        for (int r = 0; r < K; ++r) {
+            cq[r * 64] = M[r];
+            cq[(K + r) * 64] = I[r];
+            cq[(2 * K + r) * 64] = D[r];
         }
+        cq[3 * K * 64] = md;
+        cq[(3 * K + 1) * 64] = id;
+        cq[(3 * K + 2) * 64] = dd;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
-            const int s = s0 + c;
             const T mu = shift_up<P>(M[K - 1]);
             const T iu = shift_up<P>(I[K - 1]);
             const T du = shift_up<P>(D[K - 1]) + edge;
-            if (wr) {
-                T *b = bnd + (int64_t)(s + 1) * 3 * P + t;
-                b[0] = mu;
-                b[P] = iu;
-                b[2 * P] = du;
-            }
             T lam[K];
-            const char *e = pr.ecol(s);
+            const char *e = pr.ecol(s0 + c);
 #pragma unroll
             for (int r = 0; r < K; ++r) lam[r] = *(const T *)(e + r * AdjCfg<T, P, K>::ROW_BYTES);
             adj_cell_step<T, K>(M, I, D, M, I, D, mu, iu, md, id, dd, lam, pr.al, pr.be, pr.de, pr.ep, pr.ze);
@@ -259,20 +256,13 @@ __device__ __forceinline__ double adj_forward(const AdjPair<T, P, K> &pr, T *bnd
     return acc;
 }
 
-template <typename T, int P, int K, int CB>
-__device__ __forceinline__ void adj_load_block(const T *bnd, const T *ck, int q, int t, T (&cq)[3][K],
-                                               T (&bq)[CB + 1][3])
+template <typename T, int K>
+__device__ __forceinline__ void adj_load_ck(const T *ck, int q, int lane, T (&cq)[AdjCk<T, K>::V])
 {
-    const T *c0 = ck + (int64_t)q * 3 * K * P + t;
+    constexpr int V = AdjCk<T, K>::V;
+    const T *c0 = ck + (int64_t)q * V * 64 + lane;
 #pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-        for (int r = 0; r < K; ++r) cq[v][r] = c0[(v * K + r) * P];
-    const T *b0 = bnd + (int64_t)q * CB * 3 * P + t;
-#pragma unroll
-    for (int c = 0; c <= CB; ++c)
-#pragma unroll
-        for (int v = 0; v < 3; ++v) bq[c][v] = b0[(c * 3 + v) * P];
+    for (int v = 0; v < V; ++v) cq[v] = c0[v * 64];
 }
 
 // Seven row sums of forward value x backward value, per row of the lane:
@@ -282,14 +272,15 @@ struct AdjSums {
     T a[K], b[K], x[K], d[K], ei[K], ed[K], z[K];
 };
 
-// Reverse wavefront over the checkpointed forward of one pair.
+// Reverse wavefront over the checkpointed forward of the wave's pairs.
 template <typename T, int P, int K, int CB>
-__device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T *bnd, const T *ck, T bscale,
-                                             AdjSums<T, K> &A)
+__device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T *ck, T bscale, AdjSums<T, K> &A)
 {
     using C = AdjCfg<T, P, K>;
     using V2 = typename Pair2<T>::V;
+    constexpr int V = AdjCk<T, K>::V;
     const int t = pr.t, S = pr.S;
+    const T edge = (t == 0) ? (T)(ldexp(1.0, AdjRange<T>::kFwd) / (double)pr.n) : (T)0;
     // parameters of the row below the lane's last row: the next lane's first
     // row, or below the group a virtual row that only passes B_I up
     const T an_x = shift_down<P>(pr.al[0]);
@@ -307,24 +298,27 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
     T bl_dn_prev = 0;
 
     const int Q = S / CB;
-    T cn[3][K], bn[CB + 1][3];
-    adj_load_block<T, P, K, CB>(bnd, ck, Q - 1, t, cn, bn);
+    T cn[V];
+    adj_load_ck<T, K>(ck, Q - 1, pr.lane, cn);
     for (int q = Q - 1; q >= 0; --q) {
+        // F[c]: lane state before step q CB + c; bb[c]: the values received
+        // from the lane above at step q CB + c - 1 (bb[0]: from the checkpoint)
         T F[CB + 1][3][K];
         T bb[CB + 1][3];
 #pragma unroll
-        for (int v = 0; v < 3; ++v)
+        for (int v = 0; v < 3; ++v) {
 #pragma unroll
-            for (int r = 0; r < K; ++r) F[0][v][r] = cn[v][r];
-#pragma unroll
-        for (int c = 0; c <= CB; ++c)
-#pragma unroll
-            for (int v = 0; v < 3; ++v) bb[c][v] = bn[c][v];
-        if (q > 0) adj_load_block<T, P, K, CB>(bnd, ck, q - 1, t, cn, bn);
+            for (int r = 0; r < K; ++r) F[0][v][r] = cn[v * K + r];
+            bb[0][v] = cn[3 * K + v];
+        }
+        if (q > 0) adj_load_ck<T, K>(ck, q - 1, pr.lane, cn);
 
-        // recompute the block's columns from the lane's checkpoint
+        // recompute the block as a wavefront
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
+            bb[c + 1][0] = shift_up<P>(F[c][0][K - 1]);
+            bb[c + 1][1] = shift_up<P>(F[c][1][K - 1]);
+            bb[c + 1][2] = shift_up<P>(F[c][2][K - 1]) + edge;
             T lam[K];
             const char *e = pr.ecol(q * CB + c);
 #pragma unroll
@@ -411,65 +405,49 @@ __device__ __forceinline__ void adj_emit(const AdjArgs &A, const AdjPair<T, P, K
 }
 
 // ---------------------------------------------------------------------------
-// FP32 pass: one workgroup per tile of G pairs (every group of a tile uses
-// the tile's step count S, that of its first, longest record); the
-// checkpoints of a chunk of tiles live in A.ws.  Groups past the end of the
-// record list mirror group 0 and never write.
+// FP32 pass: a persistent grid drains the tiles of one (P, K) configuration.
+// Groups past the end of the record list mirror group 0 and emit nothing.
 // ---------------------------------------------------------------------------
 template <int P, int K>
-__global__ __launch_bounds__(64) void k_adj_fwd(AdjArgs A)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_adj32(AdjArgs A)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     constexpr int G = 64 / P;
-    const int first = blockIdx.x * G, idx = first + (int)threadIdx.x / P;
-    const bool valid = idx < A.nrec;
-    const AdjRec rec = A.recs[valid ? idx : first];
-    AdjPair<float, P, K> pr;
-    pr.init(A, lds, rec, __builtin_amdgcn_readlane(rec.S, 0), A.hs_bytes);
-    float *bnd = A.ws + rec.ws_off;
-    float *ck = bnd + (int64_t)(pr.S + 1) * 3 * P;
-    const double acc = adj_forward<float, P, K, kAdjC>(pr, bnd, ck, valid);
-    if (valid && pr.t == P - 1) A.Ls[idx] = acc;
-}
-
-template <int P, int K>
-__global__ __launch_bounds__(64) void k_adj_bwd(AdjArgs A)
-{
-    extern __shared__ __attribute__((aligned(16))) char lds[];
-    constexpr int G = 64 / P;
-    const int first = blockIdx.x * G, idx = first + (int)threadIdx.x / P;
-    const bool valid = idx < A.nrec;
-    const AdjRec rec = A.recs[valid ? idx : first];
-    AdjPair<float, P, K> pr;
-    pr.init(A, lds, rec, __builtin_amdgcn_readlane(rec.S, 0), A.hs_bytes);
-    const float *bnd = A.ws + rec.ws_off;
-    const float *ck = bnd + (int64_t)(pr.S + 1) * 3 * P;
-    const double Ls = A.Ls[valid ? idx : first];
-    const bool good = (Ls >= A.threshold) && (Ls <= 3.0e38);
-    const int SB = good ? AdjRange<float>::kProd - ilogb(Ls) : 0;
-    AdjSums<float, K> sums;
-    adj_backward<float, P, K, kAdjC>(pr, bnd, ck, good ? ldexpf(1.f, SB) : 0.f, sums);
-    if (!valid) return;
-    const double u = A.grad_in[rec.out];
-    if (u == 0.0) return;  // contributes nothing, whatever the pair's range
-    if (!good) {
-        // outside the FP32 range: queued for the FP64 pass, class K64 - 1 with
-        // K64 = ceil((m + 1) / 64) rows per lane
-        if (pr.t == 0) {
-            const int cls = (pr.m + 64) / 64 - 1;
-            const int slot = atomicAdd(&A.q64_count[cls], 1);
-            A.q64[(int64_t)cls * A.q64_stride + slot] = (int32_t)(A.rec_base + idx);
+    const int g = (int)threadIdx.x / P;
+    float *ck = A.ws + (int64_t)blockIdx.x * A.ws_stride;
+    for (int tile = next_tile(A.tile_next); tile < A.ntiles; tile = next_tile(A.tile_next)) {
+        const int first = tile * G, idx = first + g;
+        const bool valid = idx < A.nrec;
+        const AdjRec rec = A.recs[valid ? idx : first];
+        AdjPair<float, P, K> pr;
+        pr.init(A, lds, rec, __builtin_amdgcn_readlane(rec.S, 0), A.hs_bytes);
+        const double acc = adj_forward<float, P, K, kAdjC>(pr, ck);
+        const double Ls = __shfl(acc, g * P + P - 1);
+        const bool good = (Ls >= A.threshold) && (Ls <= 3.0e38);
+        const int SB = good ? AdjRange<float>::kProd - ilogb(Ls) : 0;
+        AdjSums<float, K> sums;
+        adj_backward<float, P, K, kAdjC>(pr, ck, good ? ldexpf(1.f, SB) : 0.f, sums);
+        const double u = valid ? A.grad_in[rec.out] : 0.0;
+        if (u != 0.0) {  // a pair with u = 0 contributes nothing, whatever its range
+            if (good) {
+                adj_emit<float, P, K>(A, pr, u, 1.0 / ldexp(Ls, SB), sums);
+            } else if (pr.t == 0) {
+                // outside the FP32 range: queued for the FP64 pass, class
+                // K64 - 1 with K64 = ceil((m + 1) / 64) rows per lane
+                const int cls = (pr.m + 64) / 64 - 1;
+                const int slot = atomicAdd(&A.q64_count[cls], 1);
+                A.q64[(int64_t)cls * A.q64_stride + slot] = (int32_t)(A.rec_base + idx);
+            }
         }
-        return;
+        __syncthreads();  // LDS tables are rebuilt for the next tile
     }
-    adj_emit<float, P, K>(A, pr, u, 1.0 / ldexp(Ls, SB), sums);
 }
 
 // ---------------------------------------------------------------------------
 // FP64 pass: a persistent grid drains the queue of class K (64 lanes x K
-// rows, reads of 64 (K-1) .. 64 K - 1 bases); workgroup b owns the slice
-// [b ws64_stride, (b+1) ws64_stride) of A.ws64 and one pair at a time.
-// Every wave leaves the loop once the shared cursor passes the queue length.
+// rows, reads of 64 (K-1) .. 64 K - 1 bases), one pair at a time per
+// workgroup.  Every wave leaves the loop once the cursor passes the queue
+// length, which the FP32 pass has finished writing before this launch.
 // ---------------------------------------------------------------------------
 template <int K>
 __global__ __launch_bounds__(64) void k_adj64(AdjArgs A)
@@ -478,25 +456,20 @@ __global__ __launch_bounds__(64) void k_adj64(AdjArgs A)
     constexpr int P = 64;
     const int cls = K - 1;
     const int count = A.q64_count[cls];
-    double *bnd = A.ws64 + (int64_t)blockIdx.x * A.ws64_stride;
-    for (;;) {
-        int item = 0;
-        if (threadIdx.x == 0) item = atomicAdd(&A.q64_next[cls], 1);
-        item = __builtin_amdgcn_readlane(item, 0);
-        if (item >= count) break;
+    double *ck = A.ws64 + (int64_t)blockIdx.x * A.ws64_stride;
+    for (int item = next_tile(&A.q64_next[cls]); item < count; item = next_tile(&A.q64_next[cls])) {
         const int32_t gi = A.q64[(int64_t)cls * A.q64_stride + item];
         const AdjRec rec = A.all_recs[gi];
         const int S = ((rec.n + P - 1 + kAdjC64 - 1) / kAdjC64) * kAdjC64;
         AdjPair<double, P, K> pr;
         pr.init(A, lds, rec, S, A.hs_bytes64);
-        double *ck = bnd + (int64_t)(S + 1) * 3 * P;
-        const double acc = adj_forward<double, P, K, kAdjC64>(pr, bnd, ck, true);
+        const double acc = adj_forward<double, P, K, kAdjC64>(pr, ck);
         const double Ls = __shfl(acc, P - 1);
         // below the FP64 range floor the pair's gradients are NaN
         const bool good = (Ls >= A.floor64) && isfinite(Ls);
         const int SB = good ? AdjRange<double>::kProd - ilogb(Ls) : 0;
         AdjSums<double, K> sums;
-        adj_backward<double, P, K, kAdjC64>(pr, bnd, ck, good ? ldexp(1.0, SB) : 0.0, sums);
+        adj_backward<double, P, K, kAdjC64>(pr, ck, good ? ldexp(1.0, SB) : 0.0, sums);
         adj_emit<double, P, K>(A, pr, A.grad_in[rec.out], good ? 1.0 / ldexp(Ls, SB) : (double)NAN, sums);
         __syncthreads();  // LDS tables are rebuilt for the next pair
     }
@@ -530,20 +503,45 @@ int adj_e_bytes(int P, int K)
 
 int adj64_e_bytes(int K) { return kCodes * K * AdjCfg<double, 64, 1>::ROW_BYTES; }
 
-hipError_t launch_adj(const AdjArgs &a, int P, int K, int tiles, bool backward, hipStream_t s)
+static int occupancy(const void *fn, size_t lds)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64, lds) != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+hipError_t launch_adj32(const AdjArgs &a, int P, int K, int grid, hipStream_t s)
 {
     const size_t lds = (size_t)adj_e_bytes(P, K) + (size_t)(64 / P) * a.hs_bytes;
-#define PH_LA(p, k)                                                                  \
-    if (P == p && K == k) {                                                          \
-        if (backward)                                                                \
-            hipLaunchKernelGGL((k_adj_bwd<p, k>), dim3(tiles), dim3(64), lds, s, a); \
-        else                                                                         \
-            hipLaunchKernelGGL((k_adj_fwd<p, k>), dim3(tiles), dim3(64), lds, s, a); \
-        return hipGetLastError();                                                    \
+#define PH_LA(p, k)                                                              \
+    if (P == p && K == k) {                                                      \
+        hipLaunchKernelGGL((k_adj32<p, k>), dim3(grid), dim3(64), lds, s, a);   \
+        return hipGetLastError();                                                \
     }
     PH_ADJ_CONFIGS(PH_LA)
 #undef PH_LA
     return hipErrorInvalidValue;
+}
+
+// resident workgroups per CU, from registers (LDS is small next to 160 KB)
+int adj32_blocks_per_cu(int P, int K)
+{
+#define PH_AO(p, k) if (P == p && K == k) return occupancy((const void *)k_adj32<p, k>, 0);
+    PH_ADJ_CONFIGS(PH_AO)
+#undef PH_AO
+    return 1;
+}
+
+int adj64_blocks_per_cu(int K)
+{
+    switch (K) {
+    case 1: return occupancy((const void *)k_adj64<1>, 0);
+    case 2: return occupancy((const void *)k_adj64<2>, 0);
+    case 3: return occupancy((const void *)k_adj64<3>, 0);
+    case 4: return occupancy((const void *)k_adj64<4>, 0);
+    case 5: return occupancy((const void *)k_adj64<5>, 0);
+    }
+    return 1;
 }
 
 hipError_t launch_adj64(const AdjArgs &a, int K, int grid, hipStream_t s)

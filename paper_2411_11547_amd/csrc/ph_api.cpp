@@ -48,6 +48,15 @@ ph_status fail(ph_status st, const char *fmt, ...)
     return st;
 }
 
+}  // namespace
+
+namespace ph {
+// the calling thread's message for ph_last_error(), set by other host sources
+void set_last_error(const char *msg) { g_err = msg ? msg : ""; }
+}  // namespace ph
+
+namespace {
+
 #define HIPCHK(x)                                                                           \
     do {                                                                                    \
         hipError_t e_ = (x);                                                                \
@@ -66,9 +75,9 @@ hipError_t g_lut_status = hipSuccess;
 std::once_flag g_lut_adj_once;
 hipError_t g_lut_adj_status = hipSuccess;
 
-constexpr int64_t kAdjWsFloats = (int64_t)1 << 29;  // 2 GiB of checkpoints per chunk
-constexpr int64_t kAdjWs64Doubles = (int64_t)1 << 28;  // 2 GiB for the FP64 pass
-constexpr int kAdj64MaxGrid = 1024;                   // FP64 pass: 4 workgroups per CU
+// adjoint checkpoint workspaces: the grid of a launch shrinks to fit
+constexpr int64_t kAdjWsFloats = (int64_t)1 << 30;    // 4 GiB, FP32 pass
+constexpr int64_t kAdjWs64Doubles = (int64_t)1 << 28;  // 2 GiB, FP64 pass
 
 int rescue_class_of(int m) { return m < 128 ? 0 : m < 256 ? 1 : m < 512 ? 2 : 3; }
 
@@ -134,6 +143,12 @@ struct ph_plan {
     int64_t class_pairs[kRescueClasses] = {0, 0, 0, 0};
     int rescue_grid[kRescueClasses] = {0, 0, 0, 0};
     int plain_K = 0, plain_grid = 0;
+    // reads longer than kMaxReadLen: one extra bin swept in windows
+    int long_bin = -1, windows = 0, long_grid = 0, long64_grid = 0;
+    int64_t long_pairs = 0, bnd_stride = 0;
+    float *d_bnd32 = nullptr;
+    double *d_bnd64 = nullptr;
+    int32_t *d_long_rescue = nullptr;
     bool single = false;   // one persistent FP32 launch over all bins
     int single_grid = 0;
 
@@ -153,9 +168,10 @@ struct ph_plan {
     hipEvent_t ev[kStageEvents] = {};
     bool stages_recorded = false;
 
-    hipGraph_t graph[3] = {};
-    hipGraphExec_t exec[3] = {};
-    std::vector<const void *> graph_key;
+    // stage graphs of the forward ([0]) and of the Viterbi score ([1])
+    hipGraph_t graph[2][3] = {};
+    hipGraphExec_t exec[2][3] = {};
+    std::vector<const void *> graph_key[2];
 
     hipStream_t last_stream = nullptr;
     bool forward_done = false;
@@ -164,30 +180,34 @@ struct ph_plan {
     std::vector<int32_t> h_rb, h_hb;
     std::vector<int64_t> h_ro, h_ho, h_out_off;
 
-    // adjoint: records grouped by (P, K), tiled, cut into chunks whose
-    // checkpoints fit the workspace
-    struct AdjChunk {
+    // adjoint: records grouped by (P, K) configuration, tiled G = 64/P at a
+    // time; one persistent launch per configuration, each workgroup with its
+    // own checkpoint slice
+    struct AdjRun {
         int P, K;
         int64_t rec_begin;
-        int32_t nrec, tiles, hs_bytes;
+        int32_t nrec, ntiles, hs_bytes, grid;
+        int64_t ws_stride;  // floats per workgroup
     };
     bool adj_built = false;
     ph_status adj_status = PH_OK;
     std::string adj_error;
-    std::vector<AdjChunk> adj_chunks;
+    std::vector<AdjRun> adj_runs;
     AdjRec *d_adj_recs = nullptr;
-    double *d_adj_Ls = nullptr;
     float *d_ws = nullptr;
+    int32_t *d_adj_ctr = nullptr;  // [2][kAdj64Classes] FP64 queue lengths, cursors; then one cursor per run
     // FP64 pass over the pairs the FP32 pass leaves out: queues per class,
     // [2][kAdj64Classes] counters (lengths, cursors), per-workgroup checkpoints
     int32_t *d_q64 = nullptr;
-    int32_t *d_q64_cnt = nullptr;
     double *d_ws64 = nullptr;
     int64_t q64_stride = 0, ws64_stride = 0;
     int32_t grid64 = 0, hs_bytes64 = 0;
     bool class64[kAdj64Classes] = {};
     hipEvent_t ev_adj[2] = {};
     bool adj_recorded = false;
+    hipGraph_t adj_graph = nullptr;
+    hipGraphExec_t adj_exec = nullptr;
+    std::vector<const void *> adj_graph_key;
 };
 
 namespace {
@@ -195,12 +215,16 @@ namespace {
 void free_plan(ph_plan *p)
 {
     if (!p) return;
-    for (int i = 0; i < 3; ++i) {
-        if (p->exec[i]) (void)hipGraphExecDestroy(p->exec[i]);
-        if (p->graph[i]) (void)hipGraphDestroy(p->graph[i]);
-    }
+    for (int v = 0; v < 2; ++v)
+        for (int i = 0; i < 3; ++i) {
+            if (p->exec[v][i]) (void)hipGraphExecDestroy(p->exec[v][i]);
+            if (p->graph[v][i]) (void)hipGraphDestroy(p->graph[v][i]);
+        }
+    if (p->adj_exec) (void)hipGraphExecDestroy(p->adj_exec);
+    if (p->adj_graph) (void)hipGraphDestroy(p->adj_graph);
     void *bufs[] = {p->d_out_offset, p->d_m2bin, p->d_bin_G, p->d_hist, p->d_recs, p->d_book, p->d_rescue, p->d_lin,
-                    p->d_adj_recs, p->d_adj_Ls, p->d_ws, p->d_q64, p->d_q64_cnt, p->d_ws64};
+                    p->d_bnd32, p->d_bnd64, p->d_long_rescue,
+                    p->d_adj_recs, p->d_ws, p->d_adj_ctr, p->d_q64, p->d_ws64};
     for (auto &e : p->ev_adj)
         if (e) (void)hipEventDestroy(e);
     for (void *b : bufs)
@@ -294,47 +318,37 @@ ph_status build_adjoint(ph_plan *p)
     });
     std::vector<AdjRec> recs(items.size());
     size_t i = 0;
-    int64_t ws_max = 0;
+    int64_t ws_total = 0;
     while (i < items.size()) {
         const int P = items[i].P, K = items[i].K, G = 64 / P;
         size_t end = i;
         while (end < items.size() && items[end].P == P && items[end].K == K) ++end;
-        // tiles of G records, chunks bounded by the workspace size
-        ph_plan::AdjChunk ch{P, K, (int64_t)i, 0, 0, 0};
-        int64_t ws = 0;
+        ph_plan::AdjRun run{P, K, (int64_t)i, (int32_t)(end - i), 0, 0, 0, 0};
+        int S_max = 0;
         for (size_t a = i; a < end; a += G) {
             const size_t b = std::min(end, a + G);
+            // the tile's first record has its longest haplotype
             const int S = ((items[a].r.n + P - 1 + kAdjC - 1) / kAdjC) * kAdjC;
-            const int64_t per = ((int64_t)(S + 1) * 3 + (int64_t)(S / kAdjC) * 3 * K) * P;
-            if (ch.tiles > 0 && ws + per * (int64_t)(b - a) > kAdjWsFloats) {
-                p->adj_chunks.push_back(ch);
-                ws_max = std::max(ws_max, ws);
-                ch = ph_plan::AdjChunk{P, K, (int64_t)a, 0, 0, 0};
-                ws = 0;
-            }
             for (size_t k = a; k < b; ++k) {
-                AdjRec &r = recs[k];
-                r = items[k].r;
-                r.S = S;
-                r.ws_off = ws;
-                ws += per;
+                recs[k] = items[k].r;
+                recs[k].S = S;
             }
-            ch.nrec += (int32_t)(b - a);
-            ch.tiles += 1;
-            const int hsb = ((S + P + 2 + 15) / 16) * 16;
-            ch.hs_bytes = std::max(ch.hs_bytes, hsb);
+            run.ntiles += 1;
+            S_max = std::max(S_max, S);
         }
-        p->adj_chunks.push_back(ch);
-        ws_max = std::max(ws_max, ws);
-        i = end;
-    }
-    for (const auto &ch : p->adj_chunks) {
-        const int64_t lds = (int64_t)adj_e_bytes(ch.P, ch.K) + (int64_t)(64 / ch.P) * ch.hs_bytes;
-        if (lds > 64 * 1024) {
+        run.hs_bytes = ((S_max + P + 2 + 15) / 16) * 16;
+        if ((int64_t)adj_e_bytes(P, K) + (int64_t)G * run.hs_bytes > 64 * 1024) {
             p->adj_status = PH_ERR_UNSUPPORTED;
             p->adj_error = "haplotype too long for the adjoint sweep";
             return p->adj_status;
         }
+        run.ws_stride = ((int64_t)(S_max / kAdjC) * (3 * K + 3) * 64 + 63) / 64 * 64;
+        const int64_t resident = (int64_t)p->cus * adj32_blocks_per_cu(P, K);
+        run.grid = (int32_t)std::max<int64_t>(
+            1, std::min<int64_t>({(int64_t)run.ntiles, resident, kAdjWsFloats / run.ws_stride}));
+        ws_total = std::max(ws_total, (int64_t)run.grid * run.ws_stride);
+        p->adj_runs.push_back(run);
+        i = end;
     }
     // FP64 pass: sized for the longest haplotype and the largest class of
     // the plan; the grid is bounded by the workspace budget
@@ -355,16 +369,16 @@ ph_status build_adjoint(ph_plan *p)
         p->adj_error = "haplotype too long for the FP64 adjoint sweep";
         return p->adj_status;
     }
-    p->ws64_stride = (((int64_t)(S64 + 1) * 3 + (int64_t)(S64 / kAdjC64) * 3 * k64_max) * 64 + 31) / 32 * 32;
+    p->ws64_stride = ((int64_t)(S64 / kAdjC64) * (3 * k64_max + 3) * 64 + 31) / 32 * 32;
     p->grid64 = (int32_t)std::max<int64_t>(
-        1, std::min<int64_t>({(int64_t)kAdj64MaxGrid, kAdjWs64Doubles / p->ws64_stride, (int64_t)items.size()}));
+        1, std::min<int64_t>({(int64_t)p->cus * adj64_blocks_per_cu(k64_max), kAdjWs64Doubles / p->ws64_stride,
+                              (int64_t)items.size()}));
     p->q64_stride = (int64_t)items.size();
     ph_status st;
     if ((st = dalloc(&p->d_adj_recs, recs.size()))) return p->adj_status = st;
-    if ((st = dalloc(&p->d_adj_Ls, recs.size()))) return p->adj_status = st;
-    if ((st = dalloc(&p->d_ws, (size_t)std::max<int64_t>(ws_max, 1)))) return p->adj_status = st;
+    if ((st = dalloc(&p->d_ws, (size_t)std::max<int64_t>(ws_total, 1)))) return p->adj_status = st;
+    if ((st = dalloc(&p->d_adj_ctr, (size_t)2 * kAdj64Classes + p->adj_runs.size()))) return p->adj_status = st;
     if ((st = dalloc(&p->d_q64, (size_t)kAdj64Classes * p->q64_stride))) return p->adj_status = st;
-    if ((st = dalloc(&p->d_q64_cnt, (size_t)2 * kAdj64Classes))) return p->adj_status = st;
     if ((st = dalloc(&p->d_ws64, (size_t)p->grid64 * p->ws64_stride))) return p->adj_status = st;
     hipError_t e = hipMemcpy(p->d_adj_recs, recs.data(), recs.size() * sizeof(AdjRec), hipMemcpyHostToDevice);
     if (e != hipSuccess) return p->adj_status = fail(PH_ERR_HIP, "hipMemcpy: %s", hipGetErrorString(e));
@@ -410,7 +424,8 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     for (int32_t r = 0; r < nr; ++r) {
         int64_t m = ro[r + 1] - ro[r];
         if (m < 1) return fail(PH_ERR_INVALID, "read %d has length %lld", r, (long long)m);
-        if (m > kMaxReadLen) return fail(PH_ERR_UNSUPPORTED, "read %d has length %lld > %d", r, (long long)m, kMaxReadLen);
+        if (m > kMaxLongReadLen)
+            return fail(PH_ERR_UNSUPPORTED, "read %d has length %lld > %d", r, (long long)m, kMaxLongReadLen);
         max_m = std::max<int32_t>(max_m, (int32_t)m);
     }
     for (int32_t h = 0; h < nh; ++h) {
@@ -451,6 +466,14 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     } else {
         p->table = default_table(opts.force_p);
     }
+    if (max_m > kMaxReadLen) {
+        // the longest bin: 64 lanes x 16 rows per window, never tuned
+        if (opts.plain) return fail(PH_ERR_UNSUPPORTED, "plain mode supports reads up to %d bases", kMaxReadLen);
+        if ((int)p->table.size() >= kMaxBins) return fail(PH_ERR_INVALID, "too many bins");
+        p->table.push_back(TuneEntry{kMaxLongReadLen, 64, kLongRows / 64});
+        p->long_bin = 0;  // bins are numbered longest first
+        p->windows = max_m / kLongRows + 1;
+    }
     const int nbins = (int)p->table.size();
     if (max_m > p->table.back().max_m)
         return fail(PH_ERR_UNSUPPORTED, "read length %d exceeds the longest configured bin (%d)", max_m,
@@ -471,19 +494,30 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
         for (int32_t h = hb[q]; h < hb[q + 1]; ++h) nsum += ho[h + 1] - ho[h];
         for (int32_t r = rb[q]; r < rb[q + 1]; ++r) {
             const int m = (int)(ro[r + 1] - ro[r]);
-            p->bin_pairs[m2bin[m]] += H;
-            p->class_pairs[rescue_class_of(m)] += H;
+            const int bin = m2bin[std::min(m, kMaxReadLen + 1)];
+            p->bin_pairs[bin] += H;
             cells += (int64_t)m * nsum;
+            if (bin == p->long_bin) {  // every pair of the long bin gets a boundary slot
+                p->long_pairs += H;
+                for (int32_t h = hb[q]; h < hb[q + 1]; ++h)
+                    p->bnd_stride = std::max<int64_t>(p->bnd_stride, 3 * (ho[h + 1] - ho[h] + 1));
+            } else {
+                p->class_pairs[rescue_class_of(m)] += H;
+            }
         }
     }
     p->cells = cells;
     p->bin_grid.assign(nbins, 0);
     for (int b = 0; b < nbins; ++b) {
-        if (!p->bin_pairs[b]) continue;
+        if (!p->bin_pairs[b] || b == p->long_bin) continue;
         const TuneEntry &e = p->table[nbins - 1 - b];
         const int64_t tiles = (p->bin_pairs[b] + binG[b] - 1) / binG[b];
         const int64_t cap = (int64_t)p->cus * fwd32_blocks_per_cu(e.P, e.K);
         p->bin_grid[b] = (int)std::min<int64_t>(tiles, cap);
+    }
+    if (p->long_pairs) {
+        p->long_grid = (int)std::min<int64_t>(p->long_pairs, (int64_t)p->cus * long32_blocks_per_cu());
+        p->long64_grid = (int)std::min<int64_t>(p->long_pairs, (int64_t)p->cus * long64_blocks_per_cu());
     }
     if (opts.single_launch && !opts.plain) {
         bool ok = true;
@@ -515,6 +549,11 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     if ((st = dalloc(&p->d_recs, std::max<int64_t>(P, 1)))) return st;
     if ((st = dalloc(&p->d_book, 1))) return st;
     if ((st = dalloc(&p->d_rescue, (size_t)kRescueClasses * std::max<int64_t>(P, 1)))) return st;
+    if (p->long_pairs) {
+        if ((st = dalloc(&p->d_bnd32, (size_t)(p->long_pairs * p->bnd_stride)))) return st;
+        if ((st = dalloc(&p->d_bnd64, (size_t)(p->long_pairs * p->bnd_stride)))) return st;
+        if ((st = dalloc(&p->d_long_rescue, (size_t)p->long_pairs))) return st;
+    }
     HIPCHK(hipMemcpy(p->d_out_offset, out_off.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(p->d_m2bin, m2bin.data(), m2bin.size() * sizeof(int16_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(p->d_bin_G, binG.data(), nbins * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -606,6 +645,9 @@ SweepArgs sweep_args(ph_plan *p, const ph_problem *pb, const double *lin, double
         a.bins[b] = {e.P, e.K};
     }
     a.plain_count = (int32_t)p->P;
+    a.long_bin = p->long_pairs ? p->long_bin : -1;
+    a.bnd_stride = p->bnd_stride;
+    a.long_rescue_list = p->d_long_rescue;
     return a;
 }
 
@@ -613,10 +655,11 @@ SweepArgs sweep_args(ph_plan *p, const ph_problem *pb, const double *lin, double
 //   0 = parameter exponentiation (explicit mode) and binning,
 //   1 = FP32 sweeps of all bins, 2 = FP64 rescue sweeps.
 ph_status enqueue_stage(ph_plan *p, int stage, const ph_problem *pb, const float *log10_params, double *out,
-                        uint8_t *status, hipStream_t s)
+                        uint8_t *status, hipStream_t s, bool viterbi)
 {
     const double *lin = log10_params ? p->d_lin : nullptr;
-    const SweepArgs sa = sweep_args(p, pb, lin, out, status);
+    SweepArgs sa = sweep_args(p, pb, lin, out, status);
+    sa.viterbi = viterbi ? 1 : 0;
     if (stage == 0) {
         if (log10_params) HIPCHK(launch_prep_params(log10_params, p->nread_bases, p->d_lin, s));
         const BinArgs ba = bin_args(p, pb);
@@ -631,13 +674,22 @@ ph_status enqueue_stage(ph_plan *p, int stage, const ph_problem *pb, const float
     } else if (stage == 1) {
         if (p->opts.plain) {
             HIPCHK(launch_plain32(sa, p->plain_K, p->plain_grid, s));
-        } else if (p->single) {
+        } else if (p->single && !viterbi) {
             HIPCHK(launch_fwd32_single(sa, p->single_grid, s));
         } else {
-            // bins longest first, round-robin over side streams forked from s
+            // bins longest first, round-robin over side streams forked from s;
+            // the windows of the long bin run in order on one stream
             HIPCHK(hipEventRecord(p->fork, s));
             bool used[kSideStreams] = {};
             int next = 0;
+            if (p->long_pairs) {
+                const int k = next++ % kSideStreams;
+                HIPCHK(hipStreamWaitEvent(p->side[k], p->fork, 0));
+                used[k] = true;
+                SweepArgs la = sa;
+                la.bnd = p->d_bnd32;
+                for (int w = 0; w < p->windows; ++w) HIPCHK(launch_long32(la, w, p->long_grid, p->side[k]));
+            }
             for (int b = 0; b < sa.num_bins; ++b) {
                 if (!p->bin_grid[b]) continue;
                 const int k = next++ % kSideStreams;
@@ -656,25 +708,94 @@ ph_status enqueue_stage(ph_plan *p, int stage, const ph_problem *pb, const float
     } else if (!p->opts.plain) {
         for (int c = 0; c < kRescueClasses; ++c)
             if (p->rescue_grid[c]) HIPCHK(launch_fwd64(sa, c, p->rescue_grid[c], s));
+        if (p->long_pairs) {
+            SweepArgs la = sa;
+            la.bnd = p->d_bnd64;
+            for (int w = 0; w < p->windows; ++w) HIPCHK(launch_long64(la, w, p->long64_grid, s));
+        }
     }
     return PH_OK;
 }
 
 void drop_graphs(ph_plan *p)
 {
-    for (int i = 0; i < 3; ++i) {
-        if (p->exec[i]) { (void)hipGraphExecDestroy(p->exec[i]); p->exec[i] = nullptr; }
-        if (p->graph[i]) { (void)hipGraphDestroy(p->graph[i]); p->graph[i] = nullptr; }
+    for (int v = 0; v < 2; ++v) {
+        for (int i = 0; i < 3; ++i) {
+            if (p->exec[v][i]) { (void)hipGraphExecDestroy(p->exec[v][i]); p->exec[v][i] = nullptr; }
+            if (p->graph[v][i]) { (void)hipGraphDestroy(p->graph[v][i]); p->graph[v][i] = nullptr; }
+        }
+        p->graph_key[v].clear();
     }
-    p->graph_key.clear();
+    if (p->adj_exec) { (void)hipGraphExecDestroy(p->adj_exec); p->adj_exec = nullptr; }
+    if (p->adj_graph) { (void)hipGraphDestroy(p->adj_graph); p->adj_graph = nullptr; }
+    p->adj_graph_key.clear();
 }
 
-}  // namespace
+// The adjoint's launch sequence: parameter preparation, zeroing of the
+// gradient and of the counters (kernels, so that the sequence can be
+// captured), one persistent FP32 launch per (P, K) configuration, then the
+// FP64 launches of the classes present.
+ph_status enqueue_backward(ph_plan *p, const ph_problem *pb, const float *log10_params,
+                           const double *grad_log10L, float *grad_params, hipStream_t s)
+{
+    if (log10_params) HIPCHK(launch_prep_params(log10_params, p->nread_bases, p->d_lin, s));
+    HIPCHK(launch_zero_f32(grad_params, p->nread_bases * 7, s));
+    HIPCHK(launch_zero_i32(p->d_adj_ctr, 2 * kAdj64Classes + (int)p->adj_runs.size(), s));
+    AdjArgs a{};
+    a.pb.read_offset = pb->read_offset;
+    a.pb.read_bases = pb->read_bases;
+    a.pb.bq = pb->base_qual;
+    a.pb.iq = pb->ins_qual;
+    a.pb.dq = pb->del_qual;
+    a.pb.gq = pb->gcp_qual;
+    a.pb.hap_offset = pb->hap_offset;
+    a.pb.hap_bases = pb->hap_bases;
+    a.lin_params = log10_params ? p->d_lin : nullptr;
+    a.ws = p->d_ws;
+    a.grad_in = grad_log10L;
+    a.grad_out = grad_params;
+    a.threshold = p->threshold;
+    a.all_recs = p->d_adj_recs;
+    a.q64 = p->d_q64;
+    a.q64_stride = p->q64_stride;
+    a.q64_count = p->d_adj_ctr;
+    a.q64_next = p->d_adj_ctr + kAdj64Classes;
+    a.ws64 = p->d_ws64;
+    a.ws64_stride = p->ws64_stride;
+    a.hs_bytes64 = p->hs_bytes64;
+    a.floor64 = std::ldexp(1.0, -1000);
+    for (size_t k = 0; k < p->adj_runs.size(); ++k) {
+        const auto &run = p->adj_runs[k];
+        a.recs = p->d_adj_recs + run.rec_begin;
+        a.rec_base = run.rec_begin;
+        a.nrec = run.nrec;
+        a.ntiles = run.ntiles;
+        a.hs_bytes = run.hs_bytes;
+        a.tile_next = p->d_adj_ctr + 2 * kAdj64Classes + k;
+        a.ws_stride = run.ws_stride;
+        HIPCHK(launch_adj32(a, run.P, run.K, run.grid, s));
+    }
+    // pairs out of the FP32 range, per class (a class whose queue stayed
+    // empty exits at once)
+    for (int k = 1; k <= kAdj64Classes; ++k)
+        if (p->class64[k - 1]) HIPCHK(launch_adj64(a, k, p->grid64, s));
+    return PH_OK;
+}
 
-extern "C" {
+void drop_stage_graphs(ph_plan *p, int v)
+{
+    for (int i = 0; i < 3; ++i) {
+        if (p->exec[v][i]) { (void)hipGraphExecDestroy(p->exec[v][i]); p->exec[v][i] = nullptr; }
+        if (p->graph[v][i]) { (void)hipGraphDestroy(p->graph[v][i]); p->graph[v][i] = nullptr; }
+    }
+    p->graph_key[v].clear();
+}
 
-ph_status ph_forward_batch(ph_plan *p, const ph_problem *pb, const float *log10_params, double *out_log10L,
-                           uint8_t *out_status, void *stream_v)
+// The forward call and the Viterbi call: the same three stages, with the
+// sum (forward) or the maximum (Viterbi) in the sweeps, each mode with its
+// own stage graphs.
+ph_status run_forward(ph_plan *p, const ph_problem *pb, const float *log10_params, double *out_log10L,
+                      uint8_t *out_status, void *stream_v, bool viterbi)
 {
     g_err.clear();
     if (!p) return fail(PH_ERR_INVALID, "plan is NULL");
@@ -684,6 +805,7 @@ ph_status ph_forward_batch(ph_plan *p, const ph_problem *pb, const float *log10_
     if (!out_log10L) return fail(PH_ERR_INVALID, "out_log10L is NULL");
     if (!log10_params && (!pb->base_qual || !pb->ins_qual || !pb->del_qual || !pb->gcp_qual))
         return fail(PH_ERR_INVALID, "Phred arrays are NULL and no log10 parameters were given");
+    if (viterbi && p->opts.plain) return fail(PH_ERR_UNSUPPORTED, "the Viterbi score needs a binned plan");
     hipStream_t s = (hipStream_t)stream_v;
     if (log10_params && p->lin_cap < p->nread_bases) {
         if (p->d_lin) HIPCHK(hipFree(p->d_lin));
@@ -692,6 +814,7 @@ ph_status ph_forward_batch(ph_plan *p, const ph_problem *pb, const float *log10_
         p->lin_cap = p->nread_bases;
         drop_graphs(p);
     }
+    const int v = viterbi ? 1 : 0;
 
     // Each stage is captured into its own graph so that HIP events recorded on
     // the caller's stream between the three launches time the stages.
@@ -700,30 +823,36 @@ ph_status ph_forward_batch(ph_plan *p, const ph_problem *pb, const float *log10_
                                          pb->read_bases, pb->base_qual, pb->ins_qual, pb->del_qual,
                                          pb->gcp_qual, pb->hap_offset, pb->hap_bases, log10_params,
                                          out_log10L, out_status};
-        if (!p->exec[0] || key != p->graph_key) {
-            drop_graphs(p);
+        if (!p->exec[v][0] || key != p->graph_key[v]) {
+            drop_stage_graphs(p, v);
             for (int stage = 0; stage < 3; ++stage) {
                 HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
-                st = enqueue_stage(p, stage, pb, log10_params, out_log10L, out_status, p->cap);
+                st = enqueue_stage(p, stage, pb, log10_params, out_log10L, out_status, p->cap, viterbi);
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(p->cap, &g);
-                if (st != PH_OK) { if (g) (void)hipGraphDestroy(g); drop_graphs(p); return st; }
-                if (e != hipSuccess) { drop_graphs(p); return fail(PH_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e)); }
-                p->graph[stage] = g;
-                e = hipGraphInstantiate(&p->exec[stage], g, nullptr, nullptr, 0);
-                if (e != hipSuccess) { drop_graphs(p); return fail(PH_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e)); }
+                if (st != PH_OK) { if (g) (void)hipGraphDestroy(g); drop_stage_graphs(p, v); return st; }
+                if (e != hipSuccess) {
+                    drop_stage_graphs(p, v);
+                    return fail(PH_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+                }
+                p->graph[v][stage] = g;
+                e = hipGraphInstantiate(&p->exec[v][stage], g, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    drop_stage_graphs(p, v);
+                    return fail(PH_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+                }
             }
-            p->graph_key = key;
+            p->graph_key[v] = key;
         }
         for (int stage = 0; stage < 3; ++stage) {
             HIPCHK(hipEventRecord(p->ev[stage], s));
-            HIPCHK(hipGraphLaunch(p->exec[stage], s));
+            HIPCHK(hipGraphLaunch(p->exec[v][stage], s));
         }
         HIPCHK(hipEventRecord(p->ev[3], s));
     } else {
         for (int stage = 0; stage < 3; ++stage) {
             HIPCHK(hipEventRecord(p->ev[stage], s));
-            st = enqueue_stage(p, stage, pb, log10_params, out_log10L, out_status, s);
+            st = enqueue_stage(p, stage, pb, log10_params, out_log10L, out_status, s, viterbi);
             if (st != PH_OK) return st;
         }
         HIPCHK(hipEventRecord(p->ev[3], s));
@@ -732,6 +861,22 @@ ph_status ph_forward_batch(ph_plan *p, const ph_problem *pb, const float *log10_
     p->stages_recorded = true;
     p->forward_done = true;
     return PH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ph_status ph_forward_batch(ph_plan *p, const ph_problem *pb, const float *log10_params, double *out_log10L,
+                           uint8_t *out_status, void *stream_v)
+{
+    return run_forward(p, pb, log10_params, out_log10L, out_status, stream_v, false);
+}
+
+ph_status ph_viterbi_batch(ph_plan *p, const ph_problem *pb, const float *log10_params, double *out_log10V,
+                           uint8_t *out_status, void *stream_v)
+{
+    return run_forward(p, pb, log10_params, out_log10V, out_status, stream_v, true);
 }
 
 ph_status ph_backward_batch(ph_plan *p, const ph_problem *pb, const float *log10_params,
@@ -755,46 +900,36 @@ ph_status ph_backward_batch(ph_plan *p, const ph_problem *pb, const float *log10
         p->lin_cap = p->nread_bases;
         drop_graphs(p);
     }
-    HIPCHK(hipEventRecord(p->ev_adj[0], s));
-    if (log10_params) HIPCHK(launch_prep_params(log10_params, p->nread_bases, p->d_lin, s));
-    HIPCHK(launch_zero_f32(grad_params, p->nread_bases * 7, s));
-    HIPCHK(launch_zero_i32(p->d_q64_cnt, 2 * kAdj64Classes, s));
-    AdjArgs a{};
-    a.pb.read_offset = pb->read_offset;
-    a.pb.read_bases = pb->read_bases;
-    a.pb.bq = pb->base_qual;
-    a.pb.iq = pb->ins_qual;
-    a.pb.dq = pb->del_qual;
-    a.pb.gq = pb->gcp_qual;
-    a.pb.hap_offset = pb->hap_offset;
-    a.pb.hap_bases = pb->hap_bases;
-    a.lin_params = log10_params ? p->d_lin : nullptr;
-    a.ws = p->d_ws;
-    a.grad_in = grad_log10L;
-    a.grad_out = grad_params;
-    a.threshold = p->threshold;
-    a.all_recs = p->d_adj_recs;
-    a.q64 = p->d_q64;
-    a.q64_stride = p->q64_stride;
-    a.q64_count = p->d_q64_cnt;
-    a.q64_next = p->d_q64_cnt + kAdj64Classes;
-    a.ws64 = p->d_ws64;
-    a.ws64_stride = p->ws64_stride;
-    a.hs_bytes64 = p->hs_bytes64;
-    a.floor64 = std::ldexp(1.0, -1000);
-    for (const auto &ch : p->adj_chunks) {
-        a.recs = p->d_adj_recs + ch.rec_begin;
-        a.rec_base = ch.rec_begin;
-        a.Ls = p->d_adj_Ls + ch.rec_begin;
-        a.nrec = ch.nrec;
-        a.hs_bytes = ch.hs_bytes;
-        HIPCHK(launch_adj(a, ch.P, ch.K, ch.tiles, false, s));
-        HIPCHK(launch_adj(a, ch.P, ch.K, ch.tiles, true, s));
+    if (p->opts.use_graph) {
+        std::vector<const void *> key = {pb->read_offset, pb->read_bases, pb->base_qual, pb->ins_qual,
+                                         pb->del_qual, pb->gcp_qual, pb->hap_offset, pb->hap_bases,
+                                         log10_params, grad_log10L, grad_params};
+        if (!p->adj_exec || key != p->adj_graph_key) {
+            if (p->adj_exec) { (void)hipGraphExecDestroy(p->adj_exec); p->adj_exec = nullptr; }
+            if (p->adj_graph) { (void)hipGraphDestroy(p->adj_graph); p->adj_graph = nullptr; }
+            HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
+            st = enqueue_backward(p, pb, log10_params, grad_log10L, grad_params, p->cap);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(p->cap, &g);
+            if (st != PH_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+            if (e != hipSuccess) return fail(PH_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            p->adj_graph = g;
+            e = hipGraphInstantiate(&p->adj_exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                p->adj_graph = nullptr;
+                p->adj_exec = nullptr;
+                return fail(PH_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            }
+            p->adj_graph_key = key;
+        }
+        HIPCHK(hipEventRecord(p->ev_adj[0], s));
+        HIPCHK(hipGraphLaunch(p->adj_exec, s));
+    } else {
+        HIPCHK(hipEventRecord(p->ev_adj[0], s));
+        st = enqueue_backward(p, pb, log10_params, grad_log10L, grad_params, s);
+        if (st != PH_OK) return st;
     }
-    // pairs out of the FP32 range, per class (a class whose queue stayed
-    // empty exits at once)
-    for (int k = 1; k <= kAdj64Classes; ++k)
-        if (p->class64[k - 1]) HIPCHK(launch_adj64(a, k, p->grid64, s));
     HIPCHK(hipEventRecord(p->ev_adj[1], s));
     p->adj_recorded = true;
     return PH_OK;

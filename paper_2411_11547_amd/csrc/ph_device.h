@@ -93,6 +93,16 @@ __device__ __forceinline__ double shift_down(double v)
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// Work cursor of a persistent loop: lane 0 takes the next index, every lane
+// reads it back with v_readlane, so the loop condition is wave-uniform and
+// the control flow stays reducible.
+__device__ __forceinline__ int next_tile(int32_t *cursor)
+{
+    int t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(cursor, 1);
+    return __builtin_amdgcn_readlane(t, 0);
+}
+
 // Parameters of one read row in linear space.  Phred mode decodes the
 // quality bytes through the FP64 table; explicit mode reads the row's
 // exponentiated parameters, written once per call by k_prep_params.

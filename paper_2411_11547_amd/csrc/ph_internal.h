@@ -24,6 +24,11 @@ constexpr int kBuckets = 128;            // haplotype-length buckets per bin
 constexpr int kMaxKeys = kMaxBins * kBuckets;
 constexpr int kMaxReadLen = 1023;        // 64 lanes x 16 rows minus the absorbing row
 constexpr int kRescueClasses = 4;        // FP64 sweep: 64 lanes x {2, 4, 8, 16} rows
+// Longer reads run in windows of kLongRows rows (64 lanes x 16 rows): the
+// window's top boundary row comes from HBM, its bottom row goes back there
+constexpr int kLongRows = 1024;
+constexpr int kMaxWindows = 64;
+constexpr int kMaxLongReadLen = kLongRows * kMaxWindows - 1;
 
 // One read/haplotype pair: indices into the problem and into the output.
 struct PairRec {
@@ -52,6 +57,9 @@ struct Book {
     int32_t rescue_count[kRescueClasses];  // FP64 queue lengths
     int32_t rescue_counter[kRescueClasses];// FP64 sweep work cursors
     int32_t bad_code;                      // validation: count of codes > 4
+    int32_t long_counter[kMaxWindows];     // FP32 windowed passes: work cursor per window
+    int32_t long64_counter[kMaxWindows];   // FP64 windowed passes: work cursor per window
+    int32_t long_rescue_count;             // FP64 queue of long pairs
 };
 
 struct BinArgs {
@@ -84,29 +92,41 @@ struct SweepArgs {
     int32_t mode;                // 0 binned FP32 + rescue, 1 plain FP32, 2 FP64 rescue
     int32_t rescue_class;        // FP64: which queue
     int32_t plain_count;         // plain: number of records (tiles of 1 pair)
+    // reads longer than kMaxReadLen: bin `long_bin`, windows of kLongRows rows
+    int32_t long_bin;            // -1 if none
+    int32_t window;              // window of this launch
+    void *bnd;                   // boundary rows, [pair slot][n_max + 1][3] of T
+    int64_t bnd_stride;          // elements per pair slot
+    int32_t *long_rescue_list;   // FP64 queue of long pairs (record indices)
+    int32_t viterbi;             // 1: max-product score (Viterbi) instead of the likelihood
 };
 
-// Adjoint: one record per pair, grouped by (P, K) and tiled G = 64/P pairs
-// at a time; every group of a tile uses the tile's step count S.
-constexpr int kAdjC = 4;    // FP32: forward steps per column checkpoint block
-constexpr int kAdjC64 = 2;  // FP64: forward steps per column checkpoint block
+// Adjoint: one record per pair, grouped by (P, K), longest haplotype first,
+// tiled G = 64/P pairs at a time; every group of a tile uses the step count S
+// of the tile's first record.  A persistent workgroup takes a tile, runs its
+// checkpointed forward into its own workspace slice, then the reverse sweep.
+// Checkpoint layout per workgroup: [S/CB][3K+3][64] values, the lane state
+// (M, I, D of its K rows) and the three diagonal registers before every CB-th
+// step.
+constexpr int kAdjC = 4;    // FP32: forward steps per checkpoint block
+constexpr int kAdjC64 = 2;  // FP64: forward steps per checkpoint block
 constexpr int kAdj64Classes = 5;  // FP64 adjoint: 64 lanes x 1..5 rows
 
 struct AdjRec {
     int32_t read, hap, out, n;
-    int64_t ws_off;  // floats into the workspace of the record's chunk
     int32_t S, pad;
 };
 
 struct AdjArgs {
     DevProblem pb;
     const double *lin_params;
-    const AdjRec *recs;   // records of one chunk of one configuration
-    int64_t rec_base;     // index of recs[0] in all_recs
-    int32_t nrec;
-    int32_t hs_bytes;     // LDS bytes per group for the staged haplotype
-    float *ws;            // checkpoints of the chunk
-    double *Ls;           // per record: scaled FP32 row-m sum
+    const AdjRec *recs;     // records of one (P, K) configuration
+    int64_t rec_base;       // index of recs[0] in all_recs
+    int32_t nrec, ntiles;
+    int32_t hs_bytes;       // LDS bytes per group for the staged haplotype
+    int32_t *tile_next;     // work cursor of this launch
+    float *ws;              // [grid][ws_stride] per-workgroup checkpoints
+    int64_t ws_stride;
     const double *grad_in;  // per output pair
     float *grad_out;        // per read base x 7
     double threshold;       // FP32 scaled-sum range floor
@@ -125,7 +145,9 @@ struct AdjArgs {
 hipError_t upload_luts_adjoint();
 bool adj_supported(int P, int K);
 int adj_e_bytes(int P, int K);
-hipError_t launch_adj(const AdjArgs &a, int P, int K, int tiles, bool backward, hipStream_t s);
+hipError_t launch_adj32(const AdjArgs &a, int P, int K, int grid, hipStream_t s);
+int adj32_blocks_per_cu(int P, int K);
+int adj64_blocks_per_cu(int K);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
 hipError_t launch_zero_i32(int32_t *p, int n, hipStream_t s);
 int adj64_e_bytes(int K);
@@ -143,6 +165,10 @@ hipError_t launch_fwd32_single(const SweepArgs &a, int grid, hipStream_t s);
 int fwd32_single_blocks_per_cu();
 bool single_supported(int P, int K);
 hipError_t launch_fwd64(const SweepArgs &a, int cls, int grid, hipStream_t s);
+hipError_t launch_long32(const SweepArgs &a, int window, int grid, hipStream_t s);
+hipError_t launch_long64(const SweepArgs &a, int window, int grid, hipStream_t s);
+int long32_blocks_per_cu();
+int long64_blocks_per_cu();
 hipError_t launch_prep_params(const float *lg, int64_t npos, double *lin, hipStream_t s);
 hipError_t launch_validate(const DevProblem &pb, int64_t nread_bases, int64_t nhap_bases,
                            Book *book, hipStream_t s);

@@ -117,38 +117,48 @@ __device__ __forceinline__ void ring_fill(uint16_t *ring, int chunk, const uint8
 
 enum { kModeBinned = 0, kModePlain = 1, kModeRescue = 2 };
 
-// Next work item of a persistent wave: lane 0 bumps the cursor and the value
-// is read back from lane 0's register with v_readlane, which does not depend
-// on which lanes are active.
-__device__ __forceinline__ int next_tile(int32_t *cursor)
-{
-    int t = 0;
-    if (threadIdx.x == 0) t = atomicAdd(cursor, 1);
-    return __builtin_amdgcn_readlane(t, 0);
-}
-
 // One anti-diagonal step of a lane: column j = s - t + 1 of rows tK+1..tK+K.
 // M, I, D hold column j-1 on entry and column j on exit; (Md, Id, Dd) are the
 // values of the row above the lane's first row at column j-1, received from
 // lane t-1 at the previous step.  The D shift folds into one v_add_f32_dpp
 // with the row-0 edge value.
-template <typename T, int P, int K>
+//
+// Windowed mode (W): the first lane's row above is a stored boundary row;
+// (tM, tI, edge) are its M, I and D at column j, zero in the other lanes.
+//
+// Viterbi mode (V): the max-product form of Eq. (1)-(3), every sum over
+// predecessor states a maximum (beta >= 0, so the pre-multiplied D still
+// folds in: beta max(I, D) = max(beta I, beta D)); the row-m accumulator
+// keeps the maximum instead of the sum.
+template <typename T, int P, int K, bool W = false, bool V = false>
 __device__ __forceinline__ void cell_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md, T &Id, T &Dd, const T *lam,
                                           const T (&al)[K], const T (&be)[K], const T (&de)[K],
-                                          const T (&ep)[K], const T (&zt)[K], T edge, T &acc)
+                                          const T (&ep)[K], const T (&zt)[K], T edge, T &acc, T tM = 0,
+                                          T tI = 0)
 {
-    const T Mu = shift_up<P>(M[K - 1]);
-    const T Iu = shift_up<P>(I[K - 1]);
+    T Mu = shift_up<P>(M[K - 1]);
+    T Iu = shift_up<P>(I[K - 1]);
     const T Du = shift_up<P>(D[K - 1]) + edge;
+    if constexpr (W) {
+        Mu += tM;
+        Iu += tI;
+    }
     T mup = Mu, iup = Iu, mdg = Md, idg = Id, ddg = Dd;
 #pragma unroll
     for (int r = 0; r < K; ++r) {
         const T mo = M[r], io = I[r], dol = D[r];
-        T x = fma(be[r], idg, ddg);
-        x = fma(al[r], mdg, x);
-        const T mn = lam[r] * x;
-        const T in = fma(ep[r], iup, de[r] * mup);
-        const T dn = fma(ep[r], dol, zt[r] * mo);
+        T mn, in, dn;
+        if constexpr (V) {
+            mn = lam[r] * fmax(fmax(al[r] * mdg, be[r] * idg), ddg);
+            in = fmax(de[r] * mup, ep[r] * iup);
+            dn = fmax(zt[r] * mo, ep[r] * dol);
+        } else {
+            T x = fma(be[r], idg, ddg);
+            x = fma(al[r], mdg, x);
+            mn = lam[r] * x;
+            in = fma(ep[r], iup, de[r] * mup);
+            dn = fma(ep[r], dol, zt[r] * mo);
+        }
         M[r] = mn;
         I[r] = in;
         D[r] = dn;
@@ -161,20 +171,55 @@ __device__ __forceinline__ void cell_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md
     Md = Mu;
     Id = Iu;
     Dd = Du;
-    acc += I[K - 1];
+    if constexpr (V)
+        acc = fmax(acc, I[K - 1]);
+    else
+        acc += I[K - 1];
+}
+
+// One step of the windowed sweep (64 lanes): lane 0 takes the staged
+// boundary values of its column, and the last lane writes the window's last
+// row at its column back to the boundary slot unless this is the final window.
+template <typename T, int K, bool V>
+__device__ __forceinline__ void window_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md, T &Id, T &Dd, const T *lam,
+                                            const T (&al)[K], const T (&be)[K], const T (&de)[K],
+                                            const T (&ep)[K], const T (&zt)[K], T edge, T &acc, const T *top,
+                                            int u, int t, bool fin, T *bnd, int s, int n)
+{
+    const T tM = top[u], tI = top[64 + u], tD = top[128 + u];
+    const bool first = t == 0;
+    cell_step<T, 64, K, true, V>(M, I, D, Md, Id, Dd, lam, al, be, de, ep, zt, first ? tD + edge : (T)0, acc,
+                              first ? tM : (T)0, first ? tI : (T)0);
+    const int j = s - 62;  // the last lane's column
+    if (!fin && t == 63 && j >= 1 && j <= n) {
+        T *b = bnd + (int64_t)j * 3;
+        b[0] = M[K - 1];
+        b[1] = I[K - 1];
+        b[2] = D[K - 1];
+    }
 }
 
 // Sweep one tile: up to G = 64/P pairs, one per lane group.  Group g takes
 // record rec_first + g (or rec_idx_list[rec_first + g]) if g < nvalid.
-template <typename T, int P, int K>
+//
+// Windowed mode (W, reads longer than kMaxReadLen; P = 64, one pair per
+// wave): the launch covers rows A.window * kLongRows + 1 .. + kLongRows of
+// the pair.  Its top boundary row (M, I and D pre-multiplied by the first
+// row's beta, columns 0..n) is read from the pair's slot `bnd_slot` of A.bnd,
+// staged 64 columns at a time in LDS, and the window's last row is written
+// back in place (column j is read at step j-1 and written at step j+62).
+// Only the window that holds the absorbing row m+1 produces the result.
+template <typename T, int P, int K, bool W = false, bool V = false>
 __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int rec_first,
-                           int nvalid, char *lds)
+                           int nvalid, char *lds, int bnd_slot = 0)
 {
     using C = Cfg<T, P, K>;
+    static_assert(!W || (P == 64 && K * P == kLongRows), "windowed sweep: 64 lanes x kLongRows / 64 rows");
     const int lane = threadIdx.x;
     const int g = lane / P;
     const int t = lane % P;
-    const bool gvalid = g < nvalid;
+    const int r0 = W ? A.window * kLongRows : 0;  // first row of the window (0-based)
+    bool gvalid = g < nvalid;
     const int ridx = gvalid ? (rec_idx_list ? rec_idx_list[rec_first + g] : rec_first + g) : 0;
 
     PairRec rec = {0, 0, 0, 0};
@@ -183,9 +228,17 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     const double *lin = A.lin_params;
     const int64_t ro = gvalid ? pb.read_offset[rec.read] : 0;
     const int m = gvalid ? (int)(pb.read_offset[rec.read + 1] - ro) : 0;
+    if constexpr (W) {
+        // a pair whose absorbing row lies in an earlier window is done
+        gvalid = gvalid && m >= r0;
+        if (!__builtin_amdgcn_readfirstlane((int)gvalid)) return;
+    }
+    const bool fin = !W || m < r0 + kLongRows;  // this window holds row m + 1
     const int n = gvalid ? rec.n : 0;
     const int64_t ho = gvalid ? pb.hap_offset[rec.hap] : 0;
     const uint8_t *hap = pb.hap_bases + ho;
+    T *bnd = W ? (T *)A.bnd + (int64_t)bnd_slot * A.bnd_stride : nullptr;
+    T *top = (T *)(lds + C::E_BYTES + C::G * C::RING_BYTES);  // windowed: [3][64] staged boundary values
 
     // the longest haplotype of the wave sets the number of steps
     int nmax = n;
@@ -213,7 +266,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             uint32_t bq[C::KP], code[C::KP];
 #pragma unroll
             for (int r = 0; r < C::KP; ++r) {
-                const int64_t pos = ro + min(t * K + r, mload - 1);
+                const int64_t pos = ro + min(r0 + t * K + r, mload - 1);
                 bq[r] = pb.bq[pos];
                 code[r] = clamp_code(pb.read_bases[pos]);
             }
@@ -223,7 +276,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
 #pragma unroll
                 for (int rr = 0; rr < C::RPP; ++rr) {
                     const int r = q * C::RPP + rr;
-                    const bool real = (r < K) && (t * K + r < m);
+                    const bool real = (r < K) && (r0 + t * K + r < m);
                     lm[rr] = real ? c_1mpf[bq[r]] : 0.f;
                     lx[rr] = real ? c_pd3f[bq[r]] : 0.f;
                 }
@@ -247,7 +300,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             uint32_t iq[K], dq[K], gq[K + 1];
 #pragma unroll
             for (int r = 0; r <= K; ++r) {
-                const int64_t pos = ro + min(t * K + r, mload - 1);
+                const int64_t pos = ro + min(r0 + t * K + r, mload - 1);
                 gq[r] = pb.gq[pos];
                 if (r < K) {
                     iq[r] = pb.iq[pos];
@@ -256,7 +309,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             }
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const int i = t * K + r;
+                const int i = r0 + t * K + r;
                 const bool real = i < m;
                 const float d = c_pf[iq[r]], z = c_pf[dq[r]];
                 al[r] = real ? (T)(1.0f - d - z) : (T)0;
@@ -265,14 +318,14 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
                 ep[r] = real ? (T)c_pf[gq[r]] : (T)1;
                 zt[r] = (real && i + 1 < m) ? (T)(c_1mpf[gq[r + 1]] * z) : (T)0;
             }
-            if (t == 0 && m > 0) edge = (T)(ldexp((double)c_1mpf[gq[0]], Range<T>::kExp) / (double)n);
+            if (t == 0 && m > 0 && r0 == 0) edge = (T)(ldexp((double)c_1mpf[gq[0]], Range<T>::kExp) / (double)n);
         }
     } else {
         // FP64 sweep or explicit parameters: one row at a time in FP64, the
         // row parameters parked in the lane's own E entries, then loaded
 #pragma unroll 1
         for (int r = 0; r < K; ++r) {
-            const int i = t * K + r;
+            const int i = r0 + t * K + r;
             const int ic = min(i, mload - 1);
             const RowPar p = load_row(pb, lin, ro + ic, c_prob);
             const double bn = load_beta(pb, lin, ro + min(i + 1, mload - 1), c_prob);
@@ -291,11 +344,11 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             ep[r] = *slot(3, r);
             zt[r] = *slot(4, r);
         }
-        if (t == 0 && m > 0) edge = (T)(ldexp(load_beta(pb, lin, ro, c_prob), Range<T>::kExp) / (double)n);
+        if (t == 0 && m > 0 && r0 == 0) edge = (T)(ldexp(load_beta(pb, lin, ro, c_prob), Range<T>::kExp) / (double)n);
         // E[c][row] = lam of the row against haplotype code c (N matches all, PAD = 0)
 #pragma unroll 1
         for (int r = 0; r < C::KP; ++r) {
-            const int i = t * K + r;
+            const int i = r0 + t * K + r;
             const int ic = min(i, mload - 1);
             const RowPar p = load_row(pb, lin, ro + ic, c_prob);
             const bool real = (r < K) && (i < m);
@@ -319,7 +372,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
 #pragma unroll
     for (int r = 0; r < K; ++r) M[r] = I[r] = D[r] = 0;
     T Md = 0, Id = 0, Dd = edge;  // row above the lane's first row, column j-1
-    double acc = 0.0;          // row-m sum; each 64-step chunk is summed in T first
+    double acc = 0.0;          // row-m sum (Viterbi: maximum); each 64-step chunk in T first
     // steps run in pairs; a step past the last column only meets PAD columns
     // in the last lane and adds exact zeros
     const int total = (nmax + P - 1 + 1) & ~1;
@@ -327,6 +380,22 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
 
     for (int s0 = 0; s0 < total; s0 += kChunk) {
         ring_fill<P>(ring, s0 / kChunk + 2, hap, n, t, C::CODE_BYTES);
+        if constexpr (W) {
+            // lane t stages the boundary row at column s0 + 1 + t, which
+            // lane 0 takes at step s0 + t (zero in window 0: the row-0 D
+            // comes from `edge`)
+            const int j = s0 + 1 + t;
+            T v0 = 0, v1 = 0, v2 = 0;
+            if (r0 > 0 && j <= n) {
+                const T *b = bnd + (int64_t)j * 3;
+                v0 = b[0];
+                v1 = b[1];
+                v2 = b[2];
+            }
+            top[t] = v0;
+            top[64 + t] = v1;
+            top[128 + t] = v2;
+        }
         __syncthreads();
         const uint16_t *hp = ring + ((s0 - t) & (kRing - 1));
         const int cnt = min(kChunk, total - s0);
@@ -335,16 +404,27 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
         load_lam<T, P, K>(la, ebase_lane + hp[0]);
         for (int u = 0; u < cnt; u += 2) {
             load_lam<T, P, K>(lb, ebase_lane + hp[u + 1]);
-            cell_step<T, P, K>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, edge, part);
-            load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
-            cell_step<T, P, K>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, edge, part);
+            if constexpr (W) {
+                window_step<T, K, V>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, edge, part, top, u, t, fin,
+                                     bnd, s0 + u, n);
+                load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
+                window_step<T, K, V>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, edge, part, top, u + 1, t,
+                                     fin, bnd, s0 + u + 1, n);
+            } else {
+                cell_step<T, P, K, false, V>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, edge, part);
+                load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
+                cell_step<T, P, K, false, V>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, edge, part);
+            }
         }
-        acc += (double)part;
+        if constexpr (V)
+            acc = fmax(acc, (double)part);
+        else
+            acc += (double)part;
         __syncthreads();
     }
 
     // ---- epilogue: the group's last lane owns the row-m sum ------------------
-    if (gvalid && t == P - 1) {
+    if (gvalid && t == P - 1 && fin) {
         const double lg = log10(acc) - (double)Range<T>::kExp * 0.30102999566398119521;
         A.out_log10[rec.out] = lg;
         if (A.mode == kModeRescue) {
@@ -352,9 +432,14 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
         } else {
             const bool ok = (acc >= A.threshold) && (acc <= 3.0e38);
             if (A.mode == kModeBinned && !ok) {
-                const int cls = m < 128 ? 0 : m < 256 ? 1 : m < 512 ? 2 : 3;
-                const int slot = atomicAdd(&A.book->rescue_count[cls], 1);
-                A.rescue_list[cls * A.rescue_stride + slot] = ridx;
+                if (W) {
+                    const int slot = atomicAdd(&A.book->long_rescue_count, 1);
+                    A.long_rescue_list[slot] = ridx;
+                } else {
+                    const int cls = m < 128 ? 0 : m < 256 ? 1 : m < 512 ? 2 : 3;
+                    const int slot = atomicAdd(&A.book->rescue_count[cls], 1);
+                    A.rescue_list[cls * A.rescue_stride + slot] = ridx;
+                }
                 if (A.out_status) A.out_status[rec.out] = 1;  // final value written by the FP64 sweep
             } else if (A.out_status) {
                 A.out_status[rec.out] = ok ? 0 : 3;
@@ -386,9 +471,12 @@ bool fwd32_supported(int P, int K)
 // cursor.  Records of a bin are ordered longest haplotype first.
 // waves per SIMD each configuration should reach (register budget 512 / W)
 constexpr int waves_for(int K) { return K <= 6 ? 4 : K <= 10 ? 3 : 2; }
+// the max-product cell keeps more temporaries live (no FMA contraction)
+constexpr int waves_for_viterbi(int K) { return K <= 5 ? 4 : K <= 8 ? 3 : 2; }
 
-template <int P, int K>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K)))) void k_fwd32(SweepArgs A, int bin)
+template <int P, int K, bool V = false>
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(V ? waves_for_viterbi(K) : waves_for(K)))) void k_fwd32(SweepArgs A, int bin)
 {
     __shared__ __attribute__((aligned(16))) char lds[Cfg<float, P, K>::LDS_BYTES];
     Book *bk = A.book;
@@ -398,7 +486,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K)
     int tile = next_tile(&bk->bin_counter[bin]);
     while (tile < ntiles) {
         const int first = rb + tile * G;
-        sweep_tile<float, P, K>(A, nullptr, first, min(G, re - first), lds);
+        sweep_tile<float, P, K, false, V>(A, nullptr, first, min(G, re - first), lds);
         tile = next_tile(&bk->bin_counter[bin]);
     }
 }
@@ -449,7 +537,7 @@ __global__ __launch_bounds__(64) void k_plain32(SweepArgs A)
 }
 
 // FP64 sweep over one rescue queue (64 lanes per pair, K rows per lane).
-template <int K>
+template <int K, bool V = false>
 __global__ __launch_bounds__(64) void k_fwd64(SweepArgs A)
 {
     __shared__ __attribute__((aligned(16))) char lds[Cfg<double, 64, K>::LDS_BYTES];
@@ -458,8 +546,39 @@ __global__ __launch_bounds__(64) void k_fwd64(SweepArgs A)
     const int32_t *list = A.rescue_list + cls * A.rescue_stride;
     int tile = next_tile(&A.book->rescue_counter[cls]);
     while (tile < count) {
-        sweep_tile<double, 64, K>(A, list, tile, 1, lds);
+        sweep_tile<double, 64, K, false, V>(A, list, tile, 1, lds);
         tile = next_tile(&A.book->rescue_counter[cls]);
+    }
+}
+
+// Windowed sweeps of reads longer than kMaxReadLen: one launch per window of
+// kLongRows rows, in window order on one stream.  FP32: the tiles of the
+// long bin (one pair each, slot = position in the bin); FP64: the long-pair
+// rescue queue (slot = queue position).  A pair whose rows end in an earlier
+// window is skipped.
+template <bool V>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_long32(SweepArgs A)
+{
+    __shared__ __attribute__((aligned(16))) char lds[Cfg<float, 64, 16>::LDS_BYTES + 3 * 64 * sizeof(float)];
+    Book *bk = A.book;
+    const int rb = bk->bin_rec_begin[A.long_bin], re = bk->bin_rec_begin[A.long_bin + 1];
+    int tile = next_tile(&bk->long_counter[A.window]);
+    while (tile < re - rb) {
+        sweep_tile<float, 64, 16, true, V>(A, nullptr, rb + tile, 1, lds, tile);
+        tile = next_tile(&bk->long_counter[A.window]);
+    }
+}
+
+template <bool V>
+__global__ __launch_bounds__(64) void k_long64(SweepArgs A)
+{
+    __shared__ __attribute__((aligned(16))) char lds[Cfg<double, 64, 16>::LDS_BYTES + 3 * 64 * sizeof(double)];
+    Book *bk = A.book;
+    const int count = bk->long_rescue_count;
+    int item = next_tile(&bk->long64_counter[A.window]);
+    while (item < count) {
+        sweep_tile<double, 64, 16, true, V>(A, A.long_rescue_list, item, 1, lds, item);
+        item = next_tile(&bk->long64_counter[A.window]);
     }
 }
 
@@ -669,8 +788,14 @@ hipError_t launch_fwd32(const SweepArgs &a_in, int P, int K, int bin, int grid, 
 {
     SweepArgs a = a_in;
     a.mode = kModeBinned;
-#define PH_L32(p, k) \
-    if (P == p && K == k) { hipLaunchKernelGGL((k_fwd32<p, k>), dim3(grid), dim3(64), 0, s, a, bin); return hipGetLastError(); }
+#define PH_L32(p, k)                                                                        \
+    if (P == p && K == k) {                                                                 \
+        if (a.viterbi)                                                                      \
+            hipLaunchKernelGGL((k_fwd32<p, k, true>), dim3(grid), dim3(64), 0, s, a, bin);  \
+        else                                                                                \
+            hipLaunchKernelGGL((k_fwd32<p, k, false>), dim3(grid), dim3(64), 0, s, a, bin); \
+        return hipGetLastError();                                                           \
+    }
     PH_FWD32_CONFIGS(PH_L32)
 #undef PH_L32
     return hipErrorInvalidValue;
@@ -707,13 +832,42 @@ hipError_t launch_fwd64(const SweepArgs &a, int cls, int grid, hipStream_t s)
     SweepArgs b = a;
     b.rescue_class = cls;
     b.mode = kModeRescue;
+#define PH_L64(k)                                                                       \
+    case k:                                                                             \
+        if (b.viterbi)                                                                  \
+            hipLaunchKernelGGL((k_fwd64<k, true>), dim3(grid), dim3(64), 0, s, b);      \
+        else                                                                            \
+            hipLaunchKernelGGL((k_fwd64<k, false>), dim3(grid), dim3(64), 0, s, b);     \
+        break;
     switch (kRescueK[cls]) {
-    case 2: hipLaunchKernelGGL(k_fwd64<2>, dim3(grid), dim3(64), 0, s, b); break;
-    case 4: hipLaunchKernelGGL(k_fwd64<4>, dim3(grid), dim3(64), 0, s, b); break;
-    case 8: hipLaunchKernelGGL(k_fwd64<8>, dim3(grid), dim3(64), 0, s, b); break;
-    case 16: hipLaunchKernelGGL(k_fwd64<16>, dim3(grid), dim3(64), 0, s, b); break;
+        PH_L64(2) PH_L64(4) PH_L64(8) PH_L64(16)
     default: return hipErrorInvalidValue;
     }
+#undef PH_L64
+    return hipGetLastError();
+}
+
+hipError_t launch_long32(const SweepArgs &a, int window, int grid, hipStream_t s)
+{
+    SweepArgs b = a;
+    b.window = window;
+    b.mode = kModeBinned;
+    if (b.viterbi)
+        hipLaunchKernelGGL(k_long32<true>, dim3(grid), dim3(64), 0, s, b);
+    else
+        hipLaunchKernelGGL(k_long32<false>, dim3(grid), dim3(64), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_long64(const SweepArgs &a, int window, int grid, hipStream_t s)
+{
+    SweepArgs b = a;
+    b.window = window;
+    b.mode = kModeRescue;
+    if (b.viterbi)
+        hipLaunchKernelGGL(k_long64<true>, dim3(grid), dim3(64), 0, s, b);
+    else
+        hipLaunchKernelGGL(k_long64<false>, dim3(grid), dim3(64), 0, s, b);
     return hipGetLastError();
 }
 
@@ -756,6 +910,9 @@ int plain32_blocks_per_cu(int K)
     }
     return 1;
 }
+
+int long32_blocks_per_cu() { return occupancy((const void *)k_long32<false>); }
+int long64_blocks_per_cu() { return occupancy((const void *)k_long64<false>); }
 
 int fwd64_blocks_per_cu(int cls)
 {

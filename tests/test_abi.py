@@ -60,10 +60,10 @@ def test_shape_validation_errors():
     bad.hap_offset = np.array([0, 0], np.int64)
     st, _ = _plan_status(bad)
     assert st == -1
-    # read longer than any compiled configuration
-    long = wl.from_strings([(["A" * 1024], ["ACGT"])])
+    # read longer than the windowed sweep's limit (64 windows of 1024 rows)
+    long = wl.from_strings([(["A" * 65536], ["ACGT"])])
     st, msg = _plan_status(long)
-    assert st == -2 and "1024" in msg
+    assert st == -2 and "65536" in msg
     # batch range outside the reads
     bad = wl.from_strings([(["ACGT"], ["ACGTT"])])
     bad.batch_read_begin = np.array([0, 2], np.int32)
@@ -85,3 +85,16 @@ def test_null_plan_calls():
     ms = (ctypes.c_float * 4)()
     assert lib.ph_plan_stage_ms(None, ms) == -1
     lib.ph_plan_destroy(None)
+
+
+def test_pipeline_shape_validation_errors():
+    """ph_pipeline_create rejects a bad batch range before touching the GPU."""
+    bad = wl.from_strings([(["ACGT"], ["ACGTT"]), (["AC"], ["AAC"])])
+    bad.batch_read_begin = np.array([0, 2, 1], np.int32)
+    shape, keep = binding.shape_of(bad)
+    opts = binding.ph_pipeline_opts_default()
+    assert opts.plan.use_graph == 1 and opts.max_subset_cells == 0
+    h = ctypes.c_void_p()
+    st = binding.load().ph_pipeline_create(ctypes.byref(shape), ctypes.byref(opts), ctypes.byref(h))
+    assert st == -1 and "bad read or haplotype range" in binding.load().ph_last_error().decode()
+    assert not h.value

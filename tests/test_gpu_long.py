@@ -1,0 +1,78 @@
+"""GPU parity of reads longer than 1023 bases (windowed sweeps of 1024 rows
+with stored boundary rows, FP32 then FP64 for pairs below the FP32 range)
+against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from gpu_util import binding, check_against_oracle, gpu_forward, oracle, say, wl
+
+pytestmark = pytest.mark.gpu
+
+LONG_M = [1024, 1025, 1500, 2047, 2048, 2049, 3000]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    yield
+
+
+def long_problem(seed=21):
+    """Two batches: long reads (window edges 1024, 2048) and a few short reads
+    against haplotypes of 40..3100 bases taken from the reads' reference, so
+    that pairs fall in the FP32 range, in the FP64 range and below it."""
+    rng = np.random.default_rng(seed)
+    ref = rng.choice(list("ACGT"), size=4000)
+    reads = []
+    for m in LONG_M + [90, 700]:
+        s0 = int(rng.integers(0, 4000 - m))
+        r = ref[s0:s0 + m].copy()
+        err = rng.random(m) < 0.01
+        r[err] = rng.choice(list("ACGTN"), size=int(err.sum()))
+        reads.append("".join(r))
+    haps = ["".join(ref[:n]) for n in (40, 1100)] + ["".join(ref[500:3600])]
+    prob = wl.from_strings([(reads[:4], haps), (reads[4:], haps[1:])])
+    prob.base_qual[:] = rng.integers(20, 41, size=len(prob.base_qual))
+    prob.ins_qual[:] = rng.integers(40, 46, size=len(prob.ins_qual))
+    prob.del_qual[:] = rng.integers(40, 46, size=len(prob.del_qual))
+    prob.gcp_qual[:] = 10
+    return prob
+
+
+def test_long_reads_against_oracle():
+    prob = long_problem()
+    say(f"long reads: {prob.num_pairs} pairs, read lengths {sorted(set(prob.read_lengths.tolist()))}")
+    got, st = gpu_forward(prob)
+    ref = oracle.forward(prob)
+    say(f"  statuses {np.bincount(st, minlength=3).tolist()}, log10 L in [{ref.min():.1f}, {ref.max():.1f}]")
+    assert (st == binding.PAIR_FP32).sum() >= 6 and (st == binding.PAIR_FP64).sum() >= 3
+    check_against_oracle(prob, got, st, ref=ref)
+
+
+def test_long_reads_forced_fp64():
+    prob = long_problem(seed=22)
+    got, st = gpu_forward(prob, rescue_threshold=float("inf"))
+    assert np.all(st != binding.PAIR_FP32)
+    check_against_oracle(prob, got, st)
+
+
+def test_long_reads_explicit_params_and_replay():
+    import torch
+    prob = long_problem(seed=23)
+    rng = np.random.default_rng(24)
+    par = oracle.params_from_phred(prob.base_qual, prob.ins_qual, prob.del_qual, prob.gcp_qual)
+    par *= 10 ** rng.uniform(-0.05, 0.05, par.shape)
+    lg = np.log10(par).astype(np.float32)
+    dev = binding.DeviceProblem(prob)
+    plan = binding.Plan(prob)
+    x = torch.from_numpy(lg).cuda()
+    out1, st1 = plan.forward(dev, log10_params=x)
+    torch.cuda.synchronize()
+    a1, s1 = out1.cpu().numpy().copy(), st1.cpu().numpy().copy()
+    out2, st2 = plan.forward(dev, log10_params=x)
+    torch.cuda.synchronize()
+    assert np.array_equal(a1.view(np.int64), out2.cpu().numpy().view(np.int64))
+    assert np.array_equal(s1, st2.cpu().numpy())
+    plan.close()
+    check_against_oracle(prob, a1, s1, log10_params=lg)

@@ -1,0 +1,88 @@
+"""GPU parity of the Viterbi score (ph_viterbi_batch: the max-product form
+of the same sweep, FP32 with FP64 rescue, windowed for long reads) against
+the FP64 oracle's max-product DP; the same tolerances as the forward."""
+import numpy as np
+import pytest
+
+from gpu_util import binding, check_against_oracle, oracle, say, wl
+from test_gpu_long import long_problem
+from test_gpu_parity import RAGGED_M, RAGGED_N, _ragged
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    yield
+
+
+def gpu_viterbi(prob, log10_params=None, **plan_kw):
+    import torch
+    dev = binding.DeviceProblem(prob)
+    plan = binding.Plan(prob, **plan_kw)
+    lp = None if log10_params is None else torch.from_numpy(np.ascontiguousarray(log10_params, np.float32)).cuda()
+    out, st = plan.viterbi(dev, lp)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().copy(), st.cpu().numpy().copy()
+    plan.close()
+    return res
+
+
+def test_viterbi_config0():
+    say("viterbi config0")
+    prob = wl.config0()
+    got, st = gpu_viterbi(prob)
+    check_against_oracle(prob, got, st, ref=oracle.viterbi(prob))
+
+
+def test_viterbi_ragged_every_bin():
+    say("viterbi ragged lengths")
+    ms, ns = RAGGED_M, RAGGED_N
+    prob = _ragged(1, [ms[:9], ms[9:18], ms[18:], [1], [], [5, 7]],
+                   [ns[:4], ns[3:8], ns[7:], [1], [10, 20], []])
+    ref = oracle.viterbi(prob)
+    for kw in (dict(), dict(use_graph=False), dict(force_p=64, use_graph=False), dict(single_launch=True)):
+        got, st = gpu_viterbi(prob, **kw)
+        check_against_oracle(prob, got, st, ref=ref)
+
+
+def test_viterbi_rescue_and_long_reads():
+    say("viterbi precision-stress subset and long reads")
+    full = wl.config3(pairs=2000)
+    idx = np.sort(np.random.default_rng(41).choice(full.num_pairs, 120, replace=False))
+    prob = full.select_pairs(idx)
+    got, st = gpu_viterbi(prob)
+    assert (st == binding.PAIR_FP64).sum() > 20
+    check_against_oracle(prob, got, st, ref=oracle.viterbi(prob))
+    prob = long_problem(seed=25)
+    got, st = gpu_viterbi(prob)
+    check_against_oracle(prob, got, st, ref=oracle.viterbi(prob))
+
+
+def test_viterbi_explicit_params_bounded_by_forward_and_graphs():
+    """Explicit parameters; V <= L for every pair; the forward's and the
+    Viterbi's stage graphs replayed alternately give the same results."""
+    import torch
+    prob = wl.config2(regions=30)
+    rng = np.random.default_rng(42)
+    par = oracle.params_from_phred(prob.base_qual, prob.ins_qual, prob.del_qual, prob.gcp_qual)
+    par *= 10 ** rng.uniform(-0.1, 0.1, par.shape)
+    lg = np.log10(par).astype(np.float32)
+    dev = binding.DeviceProblem(prob)
+    plan = binding.Plan(prob)
+    x = torch.from_numpy(lg).cuda()
+    v1, sv1 = (a.cpu().numpy().copy() for a in plan.viterbi(dev, x))
+    f1, sf1 = (a.cpu().numpy().copy() for a in plan.forward(dev, x))
+    v2, _ = (a.cpu().numpy().copy() for a in plan.viterbi(dev, x))
+    f2, _ = (a.cpu().numpy().copy() for a in plan.forward(dev, x))
+    torch.cuda.synchronize()
+    plan.close()
+    assert np.array_equal(v1.view(np.int64), v2.view(np.int64))
+    assert np.array_equal(f1.view(np.int64), f2.view(np.int64))
+    ok = (sv1 != binding.PAIR_FP64_FLOOR) & (sf1 != binding.PAIR_FP64_FLOOR)
+    assert np.all(v1[ok] <= f1[ok] + 1e-3)
+    sample = np.sort(rng.choice(prob.num_pairs, 300, replace=False))
+    ref = oracle.viterbi(prob, log10_params=lg, pairs=sample)
+    check_against_oracle(prob, v1, sv1, ref=ref, pairs=sample)
