@@ -273,7 +273,10 @@ struct AdjSums {
 };
 
 // Reverse wavefront over the checkpointed forward of the wave's pairs.
-template <typename T, int P, int K, int CB>
+// Checkpoints are R blocks of CB steps apart: fine block f of a checkpoint
+// interval is rebuilt by advancing f CB steps from the checkpoint and then
+// recomputing its CB steps into registers.
+template <typename T, int P, int K, int CB, int R = 1>
 __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T *ck, T bscale, AdjSums<T, K> &A)
 {
     using C = AdjCfg<T, P, K>;
@@ -297,10 +300,11 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
     }
     T bl_dn_prev = 0;
 
-    const int Q = S / CB;
+    const int NB = S / CB;  // fine blocks; the checkpoint of block b is b / R
     T cn[V];
-    adj_load_ck<T, K>(ck, Q - 1, pr.lane, cn);
-    for (int q = Q - 1; q >= 0; --q) {
+    adj_load_ck<T, K>(ck, (NB - 1) / R, pr.lane, cn);
+    for (int b = NB - 1; b >= 0; --b) {
+        const int q = b;  // steps of this block: q CB .. q CB + CB - 1
         // F[c]: lane state before step q CB + c; bb[c]: the values received
         // from the lane above at step q CB + c - 1 (bb[0]: from the checkpoint)
         T F[CB + 1][3][K];
@@ -311,7 +315,26 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
             for (int r = 0; r < K; ++r) F[0][v][r] = cn[v * K + r];
             bb[0][v] = cn[3 * K + v];
         }
-        if (q > 0) adj_load_ck<T, K>(ck, q - 1, pr.lane, cn);
+        if (b > 0) adj_load_ck<T, K>(ck, (b - 1) / R, pr.lane, cn);
+
+        if constexpr (R > 1) {
+            // advance from the checkpoint at step (b / R) R CB to step q CB
+#pragma unroll 1
+            for (int s = (b / R) * R * CB; s < q * CB; ++s) {
+                const T mu = shift_up<P>(F[0][0][K - 1]);
+                const T iu = shift_up<P>(F[0][1][K - 1]);
+                const T du = shift_up<P>(F[0][2][K - 1]) + edge;
+                T lam[K];
+                const char *e = pr.ecol(s);
+#pragma unroll
+                for (int r = 0; r < K; ++r) lam[r] = *(const T *)(e + r * C::ROW_BYTES);
+                adj_cell_step<T, K>(F[0][0], F[0][1], F[0][2], F[0][0], F[0][1], F[0][2], mu, iu, bb[0][0],
+                                    bb[0][1], bb[0][2], lam, pr.al, pr.be, pr.de, pr.ep, pr.ze);
+                bb[0][0] = mu;
+                bb[0][1] = iu;
+                bb[0][2] = du;
+            }
+        }
 
         // recompute the block as a wavefront
 #pragma unroll
@@ -421,12 +444,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         const AdjRec rec = A.recs[valid ? idx : first];
         AdjPair<float, P, K> pr;
         pr.init(A, lds, rec, __builtin_amdgcn_readlane(rec.S, 0), A.hs_bytes);
-        const double acc = adj_forward<float, P, K, kAdjC>(pr, ck);
+        const double acc = adj_forward<float, P, K, kAdjC * kAdjR>(pr, ck);
         const double Ls = __shfl(acc, g * P + P - 1);
         const bool good = (Ls >= A.threshold) && (Ls <= 3.0e38);
         const int SB = good ? AdjRange<float>::kProd - ilogb(Ls) : 0;
         AdjSums<float, K> sums;
-        adj_backward<float, P, K, kAdjC>(pr, ck, good ? ldexpf(1.f, SB) : 0.f, sums);
+        adj_backward<float, P, K, kAdjC, kAdjR>(pr, ck, good ? ldexpf(1.f, SB) : 0.f, sums);
         const double u = valid ? A.grad_in[rec.out] : 0.0;
         if (u != 0.0) {  // a pair with u = 0 contributes nothing, whatever its range
             if (good) {

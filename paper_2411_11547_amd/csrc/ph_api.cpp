@@ -328,7 +328,8 @@ ph_status build_adjoint(ph_plan *p)
         for (size_t a = i; a < end; a += G) {
             const size_t b = std::min(end, a + G);
             // the tile's first record has its longest haplotype
-            const int S = ((items[a].r.n + P - 1 + kAdjC - 1) / kAdjC) * kAdjC;
+            constexpr int CK = kAdjC * kAdjR;  // steps per checkpoint
+            const int S = ((items[a].r.n + P - 1 + CK - 1) / CK) * CK;
             for (size_t k = a; k < b; ++k) {
                 recs[k] = items[k].r;
                 recs[k].S = S;
@@ -342,7 +343,7 @@ ph_status build_adjoint(ph_plan *p)
             p->adj_error = "haplotype too long for the adjoint sweep";
             return p->adj_status;
         }
-        run.ws_stride = ((int64_t)(S_max / kAdjC) * (3 * K + 3) * 64 + 63) / 64 * 64;
+        run.ws_stride = ((int64_t)(S_max / (kAdjC * kAdjR)) * (3 * K + 3) * 64 + 63) / 64 * 64;
         const int64_t resident = (int64_t)p->cus * adj32_blocks_per_cu(P, K);
         run.grid = (int32_t)std::max<int64_t>(
             1, std::min<int64_t>({(int64_t)run.ntiles, resident, kAdjWsFloats / run.ws_stride}));

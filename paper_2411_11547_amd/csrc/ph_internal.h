@@ -105,10 +105,14 @@ struct SweepArgs {
 // tiled G = 64/P pairs at a time; every group of a tile uses the step count S
 // of the tile's first record.  A persistent workgroup takes a tile, runs its
 // checkpointed forward into its own workspace slice, then the reverse sweep.
-// Checkpoint layout per workgroup: [S/CB][3K+3][64] values, the lane state
-// (M, I, D of its K rows) and the three diagonal registers before every CB-th
-// step.
-constexpr int kAdjC = 4;    // FP32: forward steps per checkpoint block
+// Checkpoint layout per workgroup: [S/(CB R)][3K+3][64] values, the lane
+// state (M, I, D of its K rows) and the three diagonal registers before every
+// (CB R)-th step; the backward recomputes blocks of CB steps from them.
+constexpr int kAdjC = 4;    // FP32: forward steps per recompute block
+#ifndef PH_ADJ_R
+#define PH_ADJ_R 2
+#endif
+constexpr int kAdjR = PH_ADJ_R;  // FP32: recompute blocks per checkpoint
 constexpr int kAdjC64 = 2;  // FP64: forward steps per checkpoint block
 constexpr int kAdj64Classes = 5;  // FP64 adjoint: 64 lanes x 1..5 rows
 

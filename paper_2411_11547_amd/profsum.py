@@ -20,8 +20,14 @@ import collections
 import sqlite3
 import sys
 
-SWEEP = ("k_fwd32", "k_plain32")
+SWEEP = ("k_fwd32", "k_plain32", "k_long32")
 ADJ = ("k_adj32", "k_adj64")
+
+
+def _is_sweep(name):
+    """A forward FP32 sweep kernel (not a Viterbi instance: those carry a
+    `true` template argument)."""
+    return any(k in name for k in SWEEP) and ", true>" not in name and "<true>" not in name
 
 
 def _kernels(db):
@@ -59,7 +65,7 @@ def kernels(db):
     for name, (c, tot, gx, vg, ag, lds, scr) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
         print(f"{name[:52]:<52} {c:>5} {tot / 1e6:>10.3f} {tot / c / 1e6:>9.3f} {gx:>7} {vg:>5} {ag:>5} "
               f"{lds:>6} {scr:>7}")
-    for title, marker, members in (("FP32 sweep stage", "k_reset", SWEEP),
+    for title, marker, members in (("FP32 sweep stage (forward and Viterbi calls)", "k_reset", SWEEP),
                                    ("adjoint kernels", "k_zero_f32", ADJ)):
         sp = _spans(rows, marker, members)
         if not sp:
@@ -104,7 +110,7 @@ def _copy_and_sweep(db, counter):
         if counter not in ctrs:
             continue
         v = ctrs[counter][0]
-        if any(k in name for k in SWEEP):
+        if _is_sweep(name):
             sweep += v
         elif not name.startswith(("void ph::", "ph::")) and "copy" in name.lower():
             copy = v if copy is None else max(copy, v)  # the probe is the largest copy of the run
