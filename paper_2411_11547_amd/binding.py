@@ -379,11 +379,19 @@ class Pipeline:
 
     DATA = ("read_bases", "base_qual", "ins_qual", "del_qual", "gcp_qual", "hap_bases")
 
-    def __init__(self, problem, max_subset_cells=0, pinned=True, **plan_kw):
+    def __init__(self, problem, max_subset_cells=0, pinned=True, tune_table=None, **plan_kw):
         opts = ph_pipeline_opts_default()
         opts.max_subset_cells = int(max_subset_cells)
         for k, v in plan_kw.items():
             setattr(opts.plan, k, v)
+        # the same bin table as Plan, so that every pair gets the same lane
+        # count and hence the same rounding as in a resident plan
+        if tune_table is None and not plan_kw.get("force_p") and os.path.exists(TUNED_TABLE):
+            tune_table = TUNED_TABLE
+        if tune_table == "builtin":
+            tune_table = None
+        self._tune = tune_table.encode() if tune_table else None
+        opts.plan.tune_table_path = self._tune
         shape, self._keep = shape_of(problem)
         self.handle = ph_pipeline_create(shape, opts)
         self.num_subsets, self.num_pairs, self.num_cells = ph_pipeline_info(self.handle)

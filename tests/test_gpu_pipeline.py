@@ -1,9 +1,10 @@
 """GPU checks of the host-input streaming forward (ph_pipeline_*): results
 are identical, pair by pair and bit for bit, to one plan over the device-
-resident problem (a pair's sum does not depend on the tile it shares or on
-the subset it is in: padding columns add exact zeros), for several subset
-sizes, pinned and pageable inputs, and repeated calls; a sample is checked
-against the oracle."""
+resident problem with the same bin table (a pair's sum does not depend on
+the tile it shares or on the subset it is in: padding columns add exact
+zeros; it does depend on its lane count, which sets how columns fall into
+the 64-step partial sums), for several subset sizes, pinned and pageable
+inputs, and repeated calls; a sample is checked against the oracle."""
 import numpy as np
 import pytest
 
