@@ -102,7 +102,8 @@ typedef struct {
                               buffers and replay it */
     int plain;             /* 1: one FP32 kernel sized for the longest read, pairs
                               in output order, no binning, no rescue (baseline) */
-    int force_p;           /* 0 = tuned; else lanes per pair (16, 32 or 64) for every bin */
+    int force_p;           /* 0 = tuned; else lanes per pair (4, 8, 16, 32 or 64) for every
+                              bin (4 lanes: reads up to 63, 8 lanes: up to 127) */
     int keep_checkpoints;  /* 1: build the adjoint's tables and workspace at plan
                               time (else on the first ph_backward_batch) */
     const char *tune_table_path; /* NULL = built-in table; else a text file of

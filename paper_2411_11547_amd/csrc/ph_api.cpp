@@ -122,7 +122,17 @@ ph_status read_table(const char *path, std::vector<TuneEntry> &t)
     }
     std::sort(t.begin(), t.end(), [](const TuneEntry &a, const TuneEntry &b) { return a.max_m < b.max_m; });
     if (t.empty()) return fail(PH_ERR_INVALID, "empty tune table %s", path);
-    if ((int)t.size() > kMaxBins) return fail(PH_ERR_INVALID, "tune table has more than %d entries", kMaxBins);
+    // neighbouring ranges with the same configuration form one bin
+    std::vector<TuneEntry> merged;
+    for (const TuneEntry &e : t) {
+        if (!merged.empty() && merged.back().P == e.P && merged.back().K == e.K)
+            merged.back().max_m = e.max_m;
+        else
+            merged.push_back(e);
+    }
+    t.swap(merged);
+    if ((int)t.size() > kMaxBins - 1)
+        return fail(PH_ERR_INVALID, "tune table has more than %d distinct bins", kMaxBins - 1);
     return PH_OK;
 }
 
@@ -414,8 +424,9 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     if (nb > 0 && (!shape->batch_read_begin || !shape->batch_hap_begin))
         return fail(PH_ERR_INVALID, "batch arrays are NULL");
     if (!shape->read_offset || !shape->hap_offset) return fail(PH_ERR_INVALID, "offset arrays are NULL");
-    if (opts.force_p && opts.force_p != 16 && opts.force_p != 32 && opts.force_p != 64)
-        return fail(PH_ERR_INVALID, "force_p must be 0, 16, 32 or 64");
+    if (opts.force_p && opts.force_p != 4 && opts.force_p != 8 && opts.force_p != 16 && opts.force_p != 32 &&
+        opts.force_p != 64)
+        return fail(PH_ERR_INVALID, "force_p must be 0, 4, 8, 16, 32 or 64");
 
     // --- shape validation ---------------------------------------------------
     const int32_t *rb = shape->batch_read_begin, *hb = shape->batch_hap_begin;

@@ -12,18 +12,21 @@ namespace ph {
 
 // ---------------------------------------------------------------------------
 // lane shifts inside groups of P lanes: lane t receives lane t-1's value,
-// the first lane of each group receives 0.
+// the first lane of each group receives 0.  Groups of 4 and 8 lanes shift
+// inside 16-lane rows like groups of 16: their first lanes other than lanes
+// 0, 16, 32, 48 receive the previous group's last lane, whose callers make
+// that value drop out exactly (see the forward sweep's first-row terms).
 // ---------------------------------------------------------------------------
 template <int P>
 __device__ __forceinline__ uint32_t shift_up_zero(uint32_t v)
 {
     int x = (int)v;
-    if constexpr (P == 16) {
+    if constexpr (P == 4 || P == 8 || P == 16) {
         x = __builtin_amdgcn_mov_dpp(x, 0x111 /* row_shr:1 */, 0xf, 0xf, true);
     } else if constexpr (P == 64) {
         x = __builtin_amdgcn_mov_dpp(x, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
     } else {
-        static_assert(P == 32, "lane groups of 16, 32 or 64");
+        static_assert(P == 32, "lane groups of 4, 8, 16, 32 or 64");
         // lanes 16 and 48 take lane 15 / 47 from the previous 16-lane row,
         // the rest shift inside their row; lanes 0 and 32 keep 0.
         int t = __builtin_amdgcn_update_dpp(0, x, 0x142 /* row_bcast:15 */, 0xa, 0x1, false);

@@ -19,7 +19,7 @@ constexpr int kChunk = 64;
 constexpr int kRing = 256;
 constexpr int kRingAlloc = 320;
 
-constexpr int kMaxBins = 32;
+constexpr int kMaxBins = 48;             // length bins (tuned table + the long-read bin)
 constexpr int kBuckets = 128;            // haplotype-length buckets per bin
 constexpr int kMaxKeys = kMaxBins * kBuckets;
 constexpr int kMaxReadLen = 1023;        // 64 lanes x 16 rows minus the absorbing row

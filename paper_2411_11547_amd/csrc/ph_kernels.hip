@@ -130,11 +130,15 @@ enum { kModeBinned = 0, kModePlain = 1, kModeRescue = 2 };
 // predecessor states a maximum (beta >= 0, so the pre-multiplied D still
 // folds in: beta max(I, D) = max(beta I, beta D)); the row-m accumulator
 // keeps the maximum instead of the sum.
+//
+// epI0 is the first row's eps in its I term (the one that multiplies the
+// value received from above); it differs from ep[0] only in the first lane
+// of a group, where it is 0 (see the prologue).
 template <typename T, int P, int K, bool W = false, bool V = false>
 __device__ __forceinline__ void cell_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md, T &Id, T &Dd, const T *lam,
                                           const T (&al)[K], const T (&be)[K], const T (&de)[K],
-                                          const T (&ep)[K], const T (&zt)[K], T edge, T &acc, T tM = 0,
-                                          T tI = 0)
+                                          const T (&ep)[K], const T (&zt)[K], T epI0, T edge, T &acc,
+                                          T tM = 0, T tI = 0)
 {
     T Mu = shift_up<P>(M[K - 1]);
     T Iu = shift_up<P>(I[K - 1]);
@@ -148,15 +152,16 @@ __device__ __forceinline__ void cell_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md
     for (int r = 0; r < K; ++r) {
         const T mo = M[r], io = I[r], dol = D[r];
         T mn, in, dn;
+        const T epi = r == 0 ? epI0 : ep[r];
         if constexpr (V) {
             mn = lam[r] * fmax(fmax(al[r] * mdg, be[r] * idg), ddg);
-            in = fmax(de[r] * mup, ep[r] * iup);
+            in = fmax(de[r] * mup, epi * iup);
             dn = fmax(zt[r] * mo, ep[r] * dol);
         } else {
             T x = fma(be[r], idg, ddg);
             x = fma(al[r], mdg, x);
             mn = lam[r] * x;
-            in = fma(ep[r], iup, de[r] * mup);
+            in = fma(epi, iup, de[r] * mup);
             dn = fma(ep[r], dol, zt[r] * mo);
         }
         M[r] = mn;
@@ -183,13 +188,13 @@ __device__ __forceinline__ void cell_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md
 template <typename T, int K, bool V>
 __device__ __forceinline__ void window_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md, T &Id, T &Dd, const T *lam,
                                             const T (&al)[K], const T (&be)[K], const T (&de)[K],
-                                            const T (&ep)[K], const T (&zt)[K], T edge, T &acc, const T *top,
-                                            int u, int t, bool fin, T *bnd, int s, int n)
+                                            const T (&ep)[K], const T (&zt)[K], T epI0, T edge, T &acc,
+                                            const T *top, int u, int t, bool fin, T *bnd, int s, int n)
 {
     const T tM = top[u], tI = top[64 + u], tD = top[128 + u];
     const bool first = t == 0;
-    cell_step<T, 64, K, true, V>(M, I, D, Md, Id, Dd, lam, al, be, de, ep, zt, first ? tD + edge : (T)0, acc,
-                              first ? tM : (T)0, first ? tI : (T)0);
+    cell_step<T, 64, K, true, V>(M, I, D, Md, Id, Dd, lam, al, be, de, ep, zt, epI0, first ? tD + edge : (T)0,
+                                 acc, first ? tM : (T)0, first ? tI : (T)0);
     const int j = s - 62;  // the last lane's column
     if (!fin && t == 63 && j >= 1 && j <= n) {
         T *b = bnd + (int64_t)j * 3;
@@ -361,6 +366,19 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             }
         }
     }
+    // The first lane of a group takes the row above its first row from the
+    // boundary of the DP (row 0: M = I = 0, D = 1/n), but in groups of 4 or 8
+    // lanes the lane shift hands it the previous group's last row instead.
+    // That row is an absorbing row (rows past m: M = 0 and D = 0 exactly), so
+    // its M and D terms vanish by themselves; its I enters the first row only
+    // through beta (with the diagonal) and eps (from above), and both are set
+    // to 0 here, which is exact because row 0 has I = 0.  In later windows of
+    // a long read the row above is a real stored row and keeps its terms.
+    T epI0 = ep[0];
+    if (t == 0 && r0 == 0) {
+        be[0] = 0;
+        epI0 = 0;
+    }
     // haplotype ring: PAD everywhere (negative columns read slot 3), then chunks 0 and 1
     for (int x = t; x < kRingAlloc; x += P) ring[x] = (uint16_t)(kPad * C::CODE_BYTES);
     __syncthreads();
@@ -405,15 +423,15 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
         for (int u = 0; u < cnt; u += 2) {
             load_lam<T, P, K>(lb, ebase_lane + hp[u + 1]);
             if constexpr (W) {
-                window_step<T, K, V>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, edge, part, top, u, t, fin,
-                                     bnd, s0 + u, n);
+                window_step<T, K, V>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, epI0, edge, part, top, u, t,
+                                     fin, bnd, s0 + u, n);
                 load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
-                window_step<T, K, V>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, edge, part, top, u + 1, t,
-                                     fin, bnd, s0 + u + 1, n);
+                window_step<T, K, V>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, epI0, edge, part, top, u + 1,
+                                     t, fin, bnd, s0 + u + 1, n);
             } else {
-                cell_step<T, P, K, false, V>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, edge, part);
+                cell_step<T, P, K, false, V>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, epI0, edge, part);
                 load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
-                cell_step<T, P, K, false, V>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, edge, part);
+                cell_step<T, P, K, false, V>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, epI0, edge, part);
             }
         }
         if constexpr (V)
@@ -452,6 +470,10 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
 // compiled configurations of the FP32 sweep (lanes per pair, rows per lane)
 // ---------------------------------------------------------------------------
 #define PH_FWD32_CONFIGS(X) \
+    X(4, 2) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(4, 7) X(4, 8) X(4, 9) X(4, 10) X(4, 11) X(4, 12) \
+    X(4, 13) X(4, 14) X(4, 15) X(4, 16) \
+    X(8, 2) X(8, 3) X(8, 4) X(8, 5) X(8, 6) X(8, 7) X(8, 8) X(8, 9) X(8, 10) X(8, 11) X(8, 12) \
+    X(8, 13) X(8, 14) X(8, 15) X(8, 16) \
     X(16, 1) X(16, 2) X(16, 3) X(16, 4) X(16, 5) X(16, 6) X(16, 7) X(16, 8) \
     X(16, 9) X(16, 10) X(16, 11) X(16, 12) X(16, 13) X(16, 14) X(16, 15) X(16, 16) \
     X(32, 4) X(32, 6) X(32, 8) X(32, 10) X(32, 12) X(32, 16) \

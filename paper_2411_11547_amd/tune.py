@@ -23,14 +23,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "tune_gfx950.txt")
 
 # compiled FP32 sweep configurations (mirror of the kernel's instance list)
-CONFIGS = [(16, k) for k in range(1, 17)] + [(32, k) for k in (4, 6, 8, 10, 12, 16)] + \
+CONFIGS = [(4, k) for k in range(2, 17)] + [(8, k) for k in range(2, 17)] + \
+          [(16, k) for k in range(1, 17)] + [(32, k) for k in (4, 6, 8, 10, 12, 16)] + \
           [(64, k) for k in range(2, 17)]
 
 
 def ranges():
-    """Read-length ranges of the table, aligned with P*K - 1: 16-row steps to
-    255, then 64-row steps to 1023."""
-    out = [(max(1, 16 * k), 16 * k + 15) for k in range(16)]
+    """Read-length ranges of the table, aligned with P*K - 1: 4-row steps to
+    63, 8-row steps to 127, 16-row steps to 255, then 64-row steps to 1023."""
+    out = [(max(1, 4 * k), 4 * k + 3) for k in range(16)]
+    out += [(8 * k, 8 * k + 7) for k in range(8, 16)]
+    out += [(16 * k, 16 * k + 15) for k in range(8, 16)]
     out += [(64 * k, 64 * k + 63) for k in range(4, 16)]
     return out
 
@@ -96,7 +99,7 @@ def main():
         prob = equal_length_problem(hi, args.hap_len, args.pairs)
         dev = binding.DeviceProblem(prob)
         tried = []
-        for P in (16, 32, 64):
+        for P in (4, 8, 16, 32, 64):
             ks = sorted(k for (p, k) in CONFIGS if p == P and P * k - 1 >= hi)[:args.candidates]
             for K in ks:
                 ms = time_config(prob, dev, hi, P, K)

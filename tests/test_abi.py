@@ -70,7 +70,7 @@ def test_shape_validation_errors():
     st, _ = _plan_status(bad)
     assert st == -1
     # bad force_p
-    st, _ = _plan_status(good, force_p=8)
+    st, _ = _plan_status(good, force_p=12)
     assert st == -1
     # NULL shape
     h = ctypes.c_void_p()

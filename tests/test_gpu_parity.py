@@ -44,6 +44,27 @@ def test_lane_groups(force_p):
     check_against_oracle(prob, got, st)
 
 
+@pytest.mark.parametrize("force_p", [4, 8])
+def test_small_lane_groups_ragged(force_p):
+    """Groups of 4 and 8 lanes share 16-lane DPP rows: a group's first lane
+    receives the previous group's last (absorbing) row, whose terms must
+    drop out exactly.  Reads of every length the group size supports, mixed
+    within tiles, against the oracle; forward and Viterbi."""
+    say(f"small lane groups P={force_p}")
+    top = 4 * 16 - 1 if force_p == 4 else 8 * 16 - 1
+    ms = [m for m in range(1, top + 1) if m % 3 == 1 or m in (force_p - 1, force_p, top)]
+    prob = _ragged(31 + force_p, [ms[::2], ms[1::2]], [[1, 7, 64, 65, 200], [3, 129, 300]])
+    got, st = gpu_forward(prob, force_p=force_p)
+    check_against_oracle(prob, got, st)
+    import torch
+    dev = binding.DeviceProblem(prob)
+    plan = binding.Plan(prob, force_p=force_p)
+    v, sv = plan.viterbi(dev)
+    torch.cuda.synchronize()
+    check_against_oracle(prob, v.cpu().numpy(), sv.cpu().numpy(), ref=oracle.viterbi(prob))
+    plan.close()
+
+
 def _ragged(seed, lens_m, lens_n, related=True):
     """Batches with the given read and haplotype lengths.  related=True makes
     haplotypes mutated copies of one reference and reads error-bearing
