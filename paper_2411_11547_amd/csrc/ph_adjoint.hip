@@ -2,18 +2,23 @@
 //
 // The paper computes only the forward likelihood (arXiv 2411.11547,
 // Section II-A, Eq. 1-4).  Its derivatives follow from the same DP run
-// backwards: with B_X(i,j) = dL/dX(i,j) and B(m,.) seeded by the result
-// formula L = sum_j M(m,j) + I(m,j), every term of Eq. (1)-(3) sends its
-// coefficient back to its source cell,
+// backwards.  The state carried here is (M, I, D') with D' = beta_{i+1} D,
+// D' = zeta'_i M(i,j-1) + eps_i D'(i,j-1), zeta'_i = beta_{i+1} zeta_i, so
+// that M(i,j) = lam_ij (alpha_i M + beta_i I + D')(i-1,j-1).  With
+// B_X(i,j) = dL/dX(i,j) and B(m,.) seeded by the result formula
+// L = sum_j M(m,j) + I(m,j), every term sends its coefficient back to its
+// source cell,
 //
-//   B_M(i,j) = alpha_{i+1} Bl(i+1,j+1) + delta_{i+1} B_I(i+1,j) + zeta_i B_D(i,j+1)
-//   B_I(i,j) = beta_{i+1}  Bl(i+1,j+1) + eps_{i+1}  B_I(i+1,j)
-//   B_D(i,j) = beta_{i+1}  Bl(i+1,j+1) + eps_i      B_D(i,j+1)
-//   Bl(i,j)  = lam_ij B_M(i,j)
+//   B_M(i,j)  = alpha_{i+1} Bl(i+1,j+1) + delta_{i+1} B_I(i+1,j) + zeta'_i B_D'(i,j+1)
+//   B_I(i,j)  = beta_{i+1}  Bl(i+1,j+1) + eps_{i+1}  B_I(i+1,j)
+//   B_D'(i,j) =             Bl(i+1,j+1) + eps_i      B_D'(i,j+1)
+//   Bl(i,j)   = lam_ij B_M(i,j)
 //
 // and d log10 L / d log10 theta_i (the posterior expected number of uses of
 // theta_i) is a sum over row i of forward value x coefficient x backward
-// value, divided by L.
+// value, divided by L: beta_i's sum is over (beta_i I + D')(i-1,j-1) Bl(i,j)
+// (D' of row i-1 carries beta_i), zeta_i's over zeta'_i M(i,j-1) B_D'(i,j),
+// and eps_i's D part over eps_i D'(i,j-1) B_D'(i,j), the two betas cancelling.
 //
 // Layout: the lane structure of the forward sweep (P lanes per pair, K rows
 // per lane, lane t at column j = s - t + 1 of step s).  Memory is bounded by
@@ -50,6 +55,36 @@ hipError_t upload_luts_adjoint()
     double t[256];
     for (int q = 0; q < 256; ++q) t[q] = pow(10.0, -(double)q / 10.0);
     return hipMemcpyToSymbol(HIP_SYMBOL(c_prob), t, sizeof(t));
+}
+
+// Lane t receives lane t+1's value inside 16-lane rows (P = 16) or across
+// the wave (P = 32, 64); only the wave's last lane (row's, for P = 16)
+// receives 0, so the last lane of a 32-lane group holds the next group's
+// first lane and callers scale it away.
+template <int P>
+__device__ __forceinline__ uint32_t shift_down_raw_u(uint32_t v)
+{
+    int x = (int)v;
+    if constexpr (P == 16)
+        x = __builtin_amdgcn_mov_dpp(x, 0x101 /* row_shl:1 */, 0xf, 0xf, true);
+    else
+        x = __builtin_amdgcn_mov_dpp(x, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
+    return (uint32_t)x;
+}
+
+template <int P>
+__device__ __forceinline__ float shift_down_raw(float v)
+{
+    return __builtin_bit_cast(float, shift_down_raw_u<P>(__builtin_bit_cast(uint32_t, v)));
+}
+
+template <int P>
+__device__ __forceinline__ double shift_down_raw(double v)
+{
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    uint32_t lo = shift_down_raw_u<P>((uint32_t)u);
+    uint32_t hi = shift_down_raw_u<P>((uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 // Scaling of the two precisions.  The forward starts from D(0,j) = 2^kFwd / n.
@@ -102,9 +137,13 @@ struct AdjPair {
     AdjRec rec;
     int64_t ro;
     int m, n, S;
+    // ze holds zeta' = beta_{i+1} zeta_i: D is carried pre-multiplied by the
+    // next row's beta, D' = beta_{i+1} D, so that beta (I + D) in Eq. (1)
+    // costs one FMA (the last real row's D' is 0: nothing follows it)
     T al[K], be[K], de[K], ep[K], ze[K];
     char *E;
-    const uint8_t *hs;  // staged codes; column j sits at hs[j + P]
+    const char *El;      // the lane's column of the (lam, w) table
+    const uint16_t *hs;  // staged byte offsets of the table of each column's code; column j at hs[j + P]
 
     // S: forward steps of the pair's group (a multiple of the checkpoint
     // block); hs_bytes: LDS bytes per group for the staged haplotype.
@@ -132,7 +171,8 @@ struct AdjPair {
             *slot(1, r) = real ? (T)p.b : (T)0;
             *slot(2, r) = real ? (T)p.d : (i == m ? (T)1 : (T)0);
             *slot(3, r) = real ? (T)p.e : (T)1;
-            *slot(4, r) = real ? (T)p.z : (T)0;
+            const double bnext = (i + 1 < m) ? load_beta(pb, A.lin_params, ro + i + 1, c_prob) : 0.0;
+            *slot(4, r) = real ? (T)(p.z * bnext) : (T)0;
         }
 #pragma unroll
         for (int r = 0; r < K; ++r) {
@@ -162,20 +202,25 @@ struct AdjPair {
                 *(V2 *)(mine + c * C::CODE_BYTES + r * C::ROW_BYTES) = v;
             }
         }
-        uint8_t *h = (uint8_t *)(lds + C::E_BYTES + g * hs_bytes);
+        uint16_t *h = (uint16_t *)(lds + C::E_BYTES + g * hs_bytes);
         const uint8_t *hap = pb.hap_bases + pb.hap_offset[rec.hap];
         const int len = S + P + 2;
         for (int x = t; x < len; x += P) {
             const int j = x - P;
-            h[x] = (j >= 1 && j <= n) ? (uint8_t)clamp_code(hap[j - 1]) : (uint8_t)kPad;
+            const uint32_t c = (j >= 1 && j <= n) ? clamp_code(hap[j - 1]) : (uint32_t)kPad;
+            h[x] = (uint16_t)(c * C::CODE_BYTES);
         }
         hs = h;
+        El = mine;
         __syncthreads();
     }
 
-    __device__ __forceinline__ const char *ecol(int s) const
+    __device__ __forceinline__ const char *ecol(int s) const { return El + hs[s - t + 1 + P]; }
+
+    // D'(0, j) = beta_1 / n, scaled: the first lane's row-0 boundary
+    __device__ __forceinline__ T edge() const
     {
-        return E + (int)hs[s - t + 1 + P] * C::CODE_BYTES + lane * C::ENT;
+        return (t == 0) ? (T)(ldexp((double)be[0], AdjRange<T>::kFwd) / (double)n) : (T)0;
     }
 };
 
@@ -191,7 +236,7 @@ __device__ __forceinline__ void adj_cell_step(const T (&mo)[K], const T (&io)[K]
 {
 #pragma unroll
     for (int r = 0; r < K; ++r) {
-        const T x = fma(al[r], md, be[r] * (id + dd));
+        const T x = fma(al[r], md, fma(be[r], id, dd));
         const T mr = lam[r] * x;
         const T ir = fma(ep[r], iu, de[r] * mu);
         const T dr = fma(ep[r], do_[r], ze[r] * mo[r]);
@@ -219,14 +264,19 @@ template <typename T, int P, int K, int CB>
 __device__ __forceinline__ double adj_forward(const AdjPair<T, P, K> &pr, T *ck)
 {
     constexpr int V = AdjCk<T, K>::V;
-    const int t = pr.t, S = pr.S;
-    const T edge = (t == 0) ? (T)(ldexp(1.0, AdjRange<T>::kFwd) / (double)pr.n) : (T)0;  // D(0, j) = 1/n, scaled
+    const int S = pr.S;
+    const T edge = pr.edge();
     T M[K], I[K], D[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) M[r] = I[r] = D[r] = (T)0;
     T md = 0, id = 0, dd = edge;
-    double acc = 0.0;
+    double acc = 0.0;  // row-m sum: partial sums in T over 64 steps, then FP64
+    T part = 0;
     for (int s0 = 0; s0 < S; s0 += CB) {
+        if ((s0 & 63) == 0) {
+            acc += (double)part;
+            part = 0;
+        }
         T *cq = ck + (int64_t)(s0 / CB) * V * 64 + pr.lane;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
@@ -250,10 +300,10 @@ __device__ __forceinline__ double adj_forward(const AdjPair<T, P, K> &pr, T *ck)
             md = mu;
             id = iu;
             dd = du;
-            acc += (double)I[K - 1];
+            part += I[K - 1];
         }
     }
-    return acc;
+    return acc + (double)part;
 }
 
 template <typename T, int K>
@@ -283,14 +333,21 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
     using V2 = typename Pair2<T>::V;
     constexpr int V = AdjCk<T, K>::V;
     const int t = pr.t, S = pr.S;
-    const T edge = (t == 0) ? (T)(ldexp(1.0, AdjRange<T>::kFwd) / (double)pr.n) : (T)0;
+    const T edge = pr.edge();
     // parameters of the row below the lane's last row: the next lane's first
-    // row, or below the group a virtual row that only passes B_I up
-    const T an_x = shift_down<P>(pr.al[0]);
-    const T bn_x = shift_down<P>(pr.be[0]);
-    const T dn_x = shift_down<P>(pr.de[0]);
-    const T en_x = shift_down<P>(pr.ep[0]) + ((t == P - 1) ? (T)1 : (T)0);
-    const T edge_bi = (t == P - 1) ? bscale : (T)0;
+    // row, or below the group a virtual row that only passes B_I up.  In
+    // 32-lane groups the group's last lane receives the next group's values
+    // from the lane shift: the parameters are replaced once per tile, and the
+    // shifted B_I and Bl are multiplied by keep = 0 there.
+    // Every lane runs the shifts (a DPP move under a lane mask reads 0 from
+    // the lanes the mask turns off), and the last lane is masked afterwards.
+    const bool last = t == P - 1;
+    const T keep = last ? (T)0 : (T)1;
+    const T an_x = keep * shift_down_raw<P>(pr.al[0]);
+    const T bn_x = keep * shift_down_raw<P>(pr.be[0]);
+    const T dn_x = keep * shift_down_raw<P>(pr.de[0]);
+    const T en_x = fma(keep, shift_down_raw<P>(pr.ep[0]), (T)1 - keep);
+    const T edge_bi = last ? bscale : (T)0;
 
     T BI[K], BD[K], BL[K];
 #pragma unroll
@@ -362,8 +419,8 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
                 lam[r] = v.x;
                 w[r] = v.y;
             }
-            const T bi_dn = shift_down<P>(BI[0]) + edge_bi;
-            const T bl_dn = shift_down<P>(BL[0]);
+            const T bi_dn = fma(keep, shift_down_raw<P>(BI[0]), edge_bi);
+            const T bl_dn = keep * shift_down_raw<P>(BL[0]);  // enters B_D' of the last row directly
             T bid = bi_dn;            // B_I of the row below, this column
             T bl_below = bl_dn_prev;  // Bl of the row below, next column
 #pragma unroll
@@ -375,7 +432,7 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
                 const T en = (r == K - 1) ? en_x : pr.ep[r + 1];
                 const T tb = bnr * bld;
                 const T bi = fma(en, bid, tb);
-                const T bd = fma(pr.ep[r], BD[r], tb);
+                const T bd = fma(pr.ep[r], BD[r], bld);  // B_D' = Bl below-right + eps B_D' right
                 const T bm = fma(an, bld, fma(dn, bid, pr.ze[r] * BD[r]));
                 const T bl = lam[r] * bm;
                 // forward values around (i, j): row above at j and j-1, own row at j-1 and j
@@ -385,7 +442,7 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
                 const T idg = (r == 0) ? bb[c][1] : F[c][1][r - 1];
                 const T ddg = (r == 0) ? bb[c][2] : F[c][2][r - 1];
                 A.a[r] = fma(mdg, bl, A.a[r]);
-                A.b[r] = fma(idg + ddg, bl, A.b[r]);
+                A.b[r] = fma(fma(pr.be[r], idg, ddg), bl, A.b[r]);  // (beta I + D')_diag Bl
                 A.x[r] = fma(w[r] * F[c + 1][0][r], bm, A.x[r]);
                 A.d[r] = fma(mu, bi, A.d[r]);
                 A.ei[r] = fma(iu, bi, A.ei[r]);
@@ -414,7 +471,7 @@ __device__ __forceinline__ void adj_emit(const AdjArgs &A, const AdjPair<T, P, K
         const int i = pr.t * K + r;
         if (i >= pr.m) continue;
         const double ga = (double)pr.al[r] * (double)s.a[r] * inv;
-        const double gb = (double)pr.be[r] * (double)s.b[r] * inv;
+        const double gb = (double)s.b[r] * inv;  // beta already inside the sum
         const double gx = (double)s.x[r] * inv;
         float *o = A.grad_out + (pr.ro + i) * 7;
         atomicAdd(o + 0, (float)(u * ga));
@@ -431,8 +488,11 @@ __device__ __forceinline__ void adj_emit(const AdjArgs &A, const AdjPair<T, P, K
 // FP32 pass: a persistent grid drains the tiles of one (P, K) configuration.
 // Groups past the end of the record list mirror group 0 and emit nothing.
 // ---------------------------------------------------------------------------
+#ifndef PH_ADJ_WAVES
+#define PH_ADJ_WAVES 2
+#endif
 template <int P, int K>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_adj32(AdjArgs A)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PH_ADJ_WAVES))) void k_adj32(AdjArgs A)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     constexpr int G = 64 / P;

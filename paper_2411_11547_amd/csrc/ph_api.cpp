@@ -275,7 +275,11 @@ ph_status check_problem(const ph_plan *p, const ph_problem *pb)
 // Adjoint configuration of a read length: 32 lanes x K <= 5 rows, then 64 x K.
 bool adj_config(int m, int &P, int &K)
 {
+#ifdef PH_ADJ_WIDE
+    if (false) {
+#else
     if (m + 1 <= 32 * 5) {
+#endif
         P = 32;
         K = (m + 1 + 31) / 32;
     } else if (m + 1 <= 64 * 5) {
@@ -347,7 +351,7 @@ ph_status build_adjoint(ph_plan *p)
             run.ntiles += 1;
             S_max = std::max(S_max, S);
         }
-        run.hs_bytes = ((S_max + P + 2 + 15) / 16) * 16;
+        run.hs_bytes = ((2 * (S_max + P + 2) + 15) / 16) * 16;  // u16 per column
         if ((int64_t)adj_e_bytes(P, K) + (int64_t)G * run.hs_bytes > 64 * 1024) {
             p->adj_status = PH_ERR_UNSUPPORTED;
             p->adj_error = "haplotype too long for the adjoint sweep";
@@ -374,7 +378,7 @@ ph_status build_adjoint(ph_plan *p)
         }
     }
     const int S64 = ((n_max + 63 + kAdjC64 - 1) / kAdjC64) * kAdjC64;
-    p->hs_bytes64 = ((S64 + 64 + 2 + 15) / 16) * 16;
+    p->hs_bytes64 = ((2 * (S64 + 64 + 2) + 15) / 16) * 16;  // u16 per column
     if ((int64_t)adj64_e_bytes(k64_max) + p->hs_bytes64 > 64 * 1024) {
         p->adj_status = PH_ERR_UNSUPPORTED;
         p->adj_error = "haplotype too long for the FP64 adjoint sweep";

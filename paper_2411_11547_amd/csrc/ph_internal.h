@@ -108,7 +108,10 @@ struct SweepArgs {
 // Checkpoint layout per workgroup: [S/(CB R)][3K+3][64] values, the lane
 // state (M, I, D of its K rows) and the three diagonal registers before every
 // (CB R)-th step; the backward recomputes blocks of CB steps from them.
-constexpr int kAdjC = 4;    // FP32: forward steps per recompute block
+#ifndef PH_ADJ_C
+#define PH_ADJ_C 4
+#endif
+constexpr int kAdjC = PH_ADJ_C;  // FP32: forward steps per recompute block
 #ifndef PH_ADJ_R
 #define PH_ADJ_R 2
 #endif
