@@ -25,7 +25,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Forward GCUPS on 1 MI355X (binned FP32+FP64 rescue vs plain); adjoint GCUPS"
 FLOPS_PER_CELL = 11            # Eq. (1)-(3): 7 multiplications + 4 additions
-VALU_PER_CELL = 7              # FMA-contracted instructions per cell in the sweep
+VALU_PER_CELL = 6              # FP32 instructions per cell of the rescaled-state sweep (4 FMA + 2 MUL)
+VITERBI_VALU_PER_CELL = 9      # the max-product cell: 6 MUL + 3 MAX
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector peak
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes/clk x clock
 
@@ -279,7 +280,7 @@ def main():
                    "stage_ms": {"binning": round(float(vst.mean(axis=0)[0]), 4),
                                 "fp32_sweep": round(float(vst.mean(axis=0)[1]), 4),
                                 "fp64_rescue": round(float(vst.mean(axis=0)[2]), 4)},
-                   "fp32_valu_per_cell": 10}
+                   "fp32_valu_per_cell": VITERBI_VALU_PER_CELL}
         log(f"viterbi: {vsec * 1e3:.2f} ms/step, {viterbi['gcups']:.1f} GCUPS")
     plan.close()
 

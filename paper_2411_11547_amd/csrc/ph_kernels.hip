@@ -9,24 +9,41 @@
 // row to lane t+1 with a DPP lane shift (the paper uses warp shuffles).  The
 // haplotype is streamed through the lanes: every lane reads its column's
 // code from a per-group ring buffer in LDS.  Emissions come from a
-// per-lane table E[code][row] in LDS (Section III-B's E array), so a cell
-// costs one LDS value and seven VALU operations:
+// per-lane table E[code][row] in LDS (Section III-B's E array).
+//
+// The FP32 sweeps carry rescaled states, Ih(i,j) = beta_{i+1} I(i,j) and
+// Dh(i,j) = D(i,j) / zeta_i, so that a sum-product cell costs one LDS value
+// and six VALU operations (the max-product cell, every sum a maximum, nine):
+//
+//   X  = cD_i Dh(i-1,j-1) + Ih(i-1,j-1) ;  X = alpha_i M(i-1,j-1) + X
+//   M(i,j)  = lam_ij X
+//   Ih(i,j) = kD_i M(i-1,j) + kE_i Ih(i-1,j)
+//   Dh(i,j) = M(i,j-1) + eps_i Dh(i,j-1)
+//
+// with cD_i = beta_i zeta_{i-1}, kD_i = beta_{i+1} delta_i and
+// kE_i = beta_{i+1} eps_i / beta_i (beta_{m+1} read as 1, so that the last
+// read row carries I itself).  Every D term of Eq. (3) is zeta_i times a
+// column sum, so Dh stays within the range of M; Ih is at most I.  A row with
+// beta_i < 2^-20 (Phred gap continuation 0, or explicit parameters near it)
+// sends its pair to the FP64 sweep, which keeps the plain states with D
+// pre-multiplied by the next row's beta:
 //
 //   X  = beta_i I(i-1,j-1) + Dt(i-1,j-1) ;  X = alpha_i M(i-1,j-1) + X
 //   M(i,j) = lam_ij X
 //   I(i,j) = delta_i M(i-1,j) + eps_i I(i-1,j)
 //   Dt(i,j) = (beta_{i+1} zeta_i) M(i,j-1) + eps_i Dt(i,j-1)
 //
-// where Dt(i,j) = beta_{i+1} D(i,j) is D pre-multiplied by the next row's
-// beta, which folds Eq. (1)'s beta_i (I + D) into one FMA.
-//
 // Differences from the paper's kernel:
-//  * Rows past the read end are "absorbing": row m+1 has lam = 0,
-//    delta = eps = 1, so I(m+1,j) = M(m,j) + I(m,j), and later rows pass I
-//    down unchanged (delta = 0, eps = 1).  The last register of the group's
-//    last lane therefore always holds the quantity Section II-A sums into L,
-//    whatever m is, and no per-lane select is needed.  (The paper pads reads
-//    with N, which would change L if read at row pK.)
+//  * Rows past the read end are "absorbing".  Plain states: row m+1 has
+//    lam = 0, delta = eps = 1, so I(m+1,j) = M(m,j) + I(m,j), and later rows
+//    pass I down unchanged (delta = 0, eps = 1); the last register of the
+//    group's last lane holds the quantity Section II-A sums into L, whatever
+//    m is.  Rescaled states: row m+1 has lam = alpha = 1, so
+//    M(m+1,j) = M(m,j-1) + I(m,j-1), and its Dh (eps = 1) sums that along
+//    the row (max-product: keeps its running maximum): the row-(m+1) lane
+//    flushes it into an FP64 accumulator every 64 steps, and later rows stay
+//    exactly zero.  (The paper pads reads with
+//    N, which would change L if read at row pK.)
 //  * Columns past the haplotype end carry a PAD code whose emission is 0, so
 //    groups of one wave may have different n and still add only exact zeros.
 //  * D(0, j) = 1/n is scaled by 2^120 (FP32) or 2^1020 (FP64) so that the
@@ -96,20 +113,36 @@ __device__ __forceinline__ void load_lam(T *lam, const char *ebase)
     }
 }
 
-// Write chunk `chunk` (64 columns) of the group's haplotype into its ring,
-// as byte offsets of the code's E table (code * code_bytes).
+// Chunk `chunk` (64 columns) of the group's haplotype goes into its ring as
+// byte offsets of the code's E table (code * code_bytes), in two parts so
+// that the global-load latency overlaps a chunk of the sweep: ring_load
+// issues lane t's loads into registers (0xffff marks a column past the
+// haplotype end; nothing waits on the loads here), ring_store converts and
+// writes them.  Chunk c + 2 is loaded at the start of the sweep's chunk c and
+// written at its end, into the slot of chunk c - 2, which no lane reads after
+// the sweep's chunk c.
 template <int P>
-__device__ __forceinline__ void ring_fill(uint16_t *ring, int chunk, const uint8_t *hap, int n, int t,
-                                          int code_bytes)
+__device__ __forceinline__ void ring_load(uint32_t (&c)[kChunk / P], int chunk, const uint8_t *hap, int n, int t)
 {
-    constexpr int PER = kChunk / P;  // columns per lane
+    constexpr int PER = kChunk / P;
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+        const int col = chunk * kChunk + t * PER + b;
+        c[b] = col < n ? (uint32_t)hap[col] : 0xffffu;
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void ring_store(uint16_t *ring, int chunk, const uint32_t (&c)[kChunk / P], int t,
+                                           int code_bytes)
+{
+    constexpr int PER = kChunk / P;
     const int slot = chunk & 3;
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
-        int x = t * PER + b;
-        int col = chunk * kChunk + x;
-        const uint32_t c = col < n ? clamp_code(hap[col]) : (uint32_t)kPad;
-        const uint16_t off = (uint16_t)(c * code_bytes);
+        const int x = t * PER + b;
+        const uint32_t code = c[b] == 0xffffu ? (uint32_t)kPad : clamp_code(c[b]);
+        const uint16_t off = (uint16_t)(code * code_bytes);
         ring[slot * kChunk + x] = off;
         if (slot == 0) ring[kRing + x] = off;
     }
@@ -182,6 +215,58 @@ __device__ __forceinline__ void cell_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md
         acc += I[K - 1];
 }
 
+// The same step with the rescaled states (M, Ih, Dh) of the FP32
+// sum-product sweep; ep holds eps, cd, kd and ke the coefficients cD, kD
+// and kE of the file header.  (eM, eI, eD) are added to the values received
+// from the lane above: the first lane's row-0 boundary (eI = beta_1 / n,
+// scaled, enters through Ih since cD = 0 on the read's first row) or, in
+// windowed mode, the stored boundary row; zero in the other lanes.
+//
+// Viterbi mode (V): every sum a maximum, as in cell_step; the rescaling by
+// positive per-row factors commutes with the maximum.
+template <typename T, int P, int K, bool W = false, bool V = false>
+__device__ __forceinline__ void cell_step_hat(T (&M)[K], T (&I)[K], T (&D)[K], T &Md, T &Id, T &Dd,
+                                              const T *lam, const T (&al)[K], const T (&cd)[K],
+                                              const T (&kd)[K], const T (&ke)[K], const T (&ep)[K], T eI,
+                                              T eM = 0, T eD = 0)
+{
+    T Mu = shift_up<P>(M[K - 1]);
+    const T Iu = shift_up<P>(I[K - 1]) + eI;
+    T Du = shift_up<P>(D[K - 1]);
+    if constexpr (W) {
+        Mu += eM;
+        Du += eD;
+    }
+    T mup = Mu, iup = Iu, mdg = Md, idg = Id, ddg = Dd;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const T mo = M[r], io = I[r], dol = D[r];
+        T mn, in, dn;
+        if constexpr (V) {
+            mn = lam[r] * fmax(fmax(al[r] * mdg, idg), cd[r] * ddg);
+            in = fmax(kd[r] * mup, ke[r] * iup);
+            dn = fmax(mo, ep[r] * dol);
+        } else {
+            T x = fma(cd[r], ddg, idg);
+            x = fma(al[r], mdg, x);
+            mn = lam[r] * x;
+            in = fma(ke[r], iup, kd[r] * mup);
+            dn = fma(ep[r], dol, mo);
+        }
+        M[r] = mn;
+        I[r] = in;
+        D[r] = dn;
+        mdg = mo;
+        idg = io;
+        ddg = dol;
+        mup = mn;
+        iup = in;
+    }
+    Md = Mu;
+    Id = Iu;
+    Dd = Du;
+}
+
 // One step of the windowed sweep (64 lanes): lane 0 takes the staged
 // boundary values of its column, and the last lane writes the window's last
 // row at its column back to the boundary slot unless this is the final window.
@@ -204,22 +289,53 @@ __device__ __forceinline__ void window_step(T (&M)[K], T (&I)[K], T (&D)[K], T &
     }
 }
 
+// window_step with the rescaled states: the staged boundary row holds
+// (M, Ih, Dh) and the row-0 boundary enters through Ih.
+template <typename T, int K, bool V>
+__device__ __forceinline__ void window_step_hat(T (&M)[K], T (&I)[K], T (&D)[K], T &Md, T &Id, T &Dd,
+                                                const T *lam, const T (&al)[K], const T (&cd)[K],
+                                                const T (&kd)[K], const T (&ke)[K], const T (&ep)[K], T edge,
+                                                const T *top, int u, int t, bool fin, T *bnd, int s, int n)
+{
+    const T tM = top[u], tI = top[64 + u], tD = top[128 + u];
+    const bool first = t == 0;
+    cell_step_hat<T, 64, K, true, V>(M, I, D, Md, Id, Dd, lam, al, cd, kd, ke, ep, first ? tI + edge : (T)0,
+                                     first ? tM : (T)0, first ? tD : (T)0);
+    const int j = s - 62;  // the last lane's column
+    if (!fin && t == 63 && j >= 1 && j <= n) {
+        T *b = bnd + (int64_t)j * 3;
+        b[0] = M[K - 1];
+        b[1] = I[K - 1];
+        b[2] = D[K - 1];
+    }
+}
+
+// beta of read position pos below 2^-20: the rescaled states cannot carry
+// that row (kE divides by beta)
+__device__ __forceinline__ bool beta_tiny(const DevProblem &pb, const double *lin, int64_t pos)
+{
+    if (lin) return !(lin[pos * 8 + 1] >= 0x1p-20);
+    return !(c_1mpf[pb.gq[pos]] >= 0x1p-20f);
+}
+
 // Sweep one tile: up to G = 64/P pairs, one per lane group.  Group g takes
 // record rec_first + g (or rec_idx_list[rec_first + g]) if g < nvalid.
 //
 // Windowed mode (W, reads longer than kMaxReadLen; P = 64, one pair per
 // wave): the launch covers rows A.window * kLongRows + 1 .. + kLongRows of
-// the pair.  Its top boundary row (M, I and D pre-multiplied by the first
-// row's beta, columns 0..n) is read from the pair's slot `bnd_slot` of A.bnd,
-// staged 64 columns at a time in LDS, and the window's last row is written
-// back in place (column j is read at step j-1 and written at step j+62).
-// Only the window that holds the absorbing row m+1 produces the result.
+// the pair.  Its top boundary row (the states of the row above, columns
+// 0..n) is read from the pair's slot `bnd_slot` of A.bnd, staged 64 columns
+// at a time in LDS, and the window's last row is written back in place
+// (column j is read at step j-1 and written at step j+62).  Only the window
+// that holds the absorbing row m+1 produces the result.
 template <typename T, int P, int K, bool W = false, bool V = false>
 __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int rec_first,
                            int nvalid, char *lds, int bnd_slot = 0)
 {
     using C = Cfg<T, P, K>;
     static_assert(!W || (P == 64 && K * P == kLongRows), "windowed sweep: 64 lanes x kLongRows / 64 rows");
+    // rescaled states (M, Ih, Dh) for the FP32 sweeps
+    constexpr bool HAT = sizeof(T) == 4;
     const int lane = threadIdx.x;
     const int g = lane / P;
     const int t = lane % P;
@@ -253,7 +369,11 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
 
     // ---- prologue: parameters of my rows, my slice of the E table ----------
     // Loads use clamped row indices so that they stay inside the read;
-    // padding rows then get their absorbing parameters by select.
+    // padding rows then get their absorbing parameters by select.  With the
+    // rescaled states the absorbing row m (0-based) has lam = 1 for every
+    // code and alpha = eps = 1, the rows past it are all zero, and the read's
+    // first row has alpha = cD = kD = kE = 0 (the row above it is the DP
+    // boundary: M = I = 0, its D enters as the Ih edge value).
     char *E = lds;
     char *mine = E + lane * 8;
     uint16_t *ring = (uint16_t *)(lds + C::E_BYTES + g * C::RING_BYTES);
@@ -261,8 +381,11 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
         return (T *)(mine + c * C::CODE_BYTES + (r / C::RPP) * 512 + (r % C::RPP) * (int)sizeof(T));
     };
     const int mload = m > 0 ? m : 1;
-    T al[K], be[K], de[K], ep[K], zt[K];
+    const int base = r0 + t * K;  // my first row (0-based)
+    T al[K], be[K], de[K], ep[K], zt[K];  // plain states
+    T cd[K], kd[K], ke[K];                // rescaled states (with al and ep)
     T edge = 0;
+    bool bad = false;  // rescaled states: one of my rows has beta below 2^-20
     if (sizeof(T) == 4 && !lin) {
         // FP32 sweep, Phred mode: all of the lane's loads issued at once,
         // decoded through the FP32 tables (1 - p and p/3 rounded from FP64);
@@ -271,17 +394,19 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             uint32_t bq[C::KP], code[C::KP];
 #pragma unroll
             for (int r = 0; r < C::KP; ++r) {
-                const int64_t pos = ro + min(r0 + t * K + r, mload - 1);
+                const int64_t pos = ro + min(base + r, mload - 1);
                 bq[r] = pb.bq[pos];
                 code[r] = clamp_code(pb.read_bases[pos]);
             }
 #pragma unroll
             for (int q = 0; q < C::NPL; ++q) {
                 float lm[C::RPP], lx[C::RPP];
+                bool one[C::RPP];
 #pragma unroll
                 for (int rr = 0; rr < C::RPP; ++rr) {
                     const int r = q * C::RPP + rr;
-                    const bool real = (r < K) && (r0 + t * K + r < m);
+                    const bool real = (r < K) && (base + r < m);
+                    one[rr] = HAT && (r < K) && (base + r == m);
                     lm[rr] = real ? c_1mpf[bq[r]] : 0.f;
                     lx[rr] = real ? c_pd3f[bq[r]] : 0.f;
                 }
@@ -292,7 +417,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
                     for (int rr = 0; rr < C::RPP; ++rr) {
                         const int r = q * C::RPP + rr;
                         const bool match = code[r] == (uint32_t)c || code[r] == 4u || c == 4;
-                        v[rr] = c == kPad ? (T)0 : (T)(match ? lm[rr] : lx[rr]);
+                        v[rr] = one[rr] ? (T)1 : c == kPad ? (T)0 : (T)(match ? lm[rr] : lx[rr]);
                     }
                     if constexpr (sizeof(T) == 4)
                         *(float2 *)(mine + c * C::CODE_BYTES + q * 512) = make_float2(v[0], v[1]);
@@ -302,26 +427,37 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             }
         }
         {
-            uint32_t iq[K], dq[K], gq[K + 1];
+            // dq[r]: row base + r - 1 (the row above row r); gq[r]: row base + r
+            uint32_t iq[K], dq[K + 1], gq[K + 1];
 #pragma unroll
             for (int r = 0; r <= K; ++r) {
-                const int64_t pos = ro + min(r0 + t * K + r, mload - 1);
-                gq[r] = pb.gq[pos];
-                if (r < K) {
-                    iq[r] = pb.iq[pos];
-                    dq[r] = pb.dq[pos];
-                }
+                gq[r] = pb.gq[ro + min(base + r, mload - 1)];
+                dq[r] = pb.dq[ro + min(max(base + r - 1, 0), mload - 1)];
+                if (r < K) iq[r] = pb.iq[ro + min(base + r, mload - 1)];
             }
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const int i = r0 + t * K + r;
+                const int i = base + r;
                 const bool real = i < m;
-                const float d = c_pf[iq[r]], z = c_pf[dq[r]];
-                al[r] = real ? (T)(1.0f - d - z) : (T)0;
-                be[r] = real ? (T)c_1mpf[gq[r]] : (T)0;
-                de[r] = real ? (T)d : (i == m ? (T)1 : (T)0);
-                ep[r] = real ? (T)c_pf[gq[r]] : (T)1;
-                zt[r] = (real && i + 1 < m) ? (T)(c_1mpf[gq[r + 1]] * z) : (T)0;
+                const float d = c_pf[iq[r]], z = c_pf[dq[r + 1]];
+                if constexpr (HAT) {
+                    const bool inner = real && i >= 1;
+                    const float b = c_1mpf[gq[r]], e = c_pf[gq[r]];
+                    const float bn = i + 1 < m ? c_1mpf[gq[r + 1]] : 1.0f;
+                    const bool ok = b >= 0x1p-20f;
+                    bad = bad || (inner && !ok);
+                    al[r] = i == 0 ? (T)0 : real ? (T)(1.0f - d - z) : (i == m ? (T)1 : (T)0);
+                    cd[r] = inner ? (T)(b * c_pf[dq[r]]) : (T)0;
+                    kd[r] = inner ? (T)(bn * d) : (T)0;
+                    ke[r] = (inner && ok) ? (T)(bn * e / b) : (T)0;
+                    ep[r] = real ? (T)e : (i == m ? (T)1 : (T)0);
+                } else {
+                    al[r] = real ? (T)(1.0f - d - z) : (T)0;
+                    be[r] = real ? (T)c_1mpf[gq[r]] : (T)0;
+                    de[r] = real ? (T)d : (i == m ? (T)1 : (T)0);
+                    ep[r] = real ? (T)c_pf[gq[r]] : (T)1;
+                    zt[r] = (real && i + 1 < m) ? (T)(c_1mpf[gq[r + 1]] * z) : (T)0;
+                }
             }
             if (t == 0 && m > 0 && r0 == 0) edge = (T)(ldexp((double)c_1mpf[gq[0]], Range<T>::kExp) / (double)n);
         }
@@ -330,78 +466,136 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
         // row parameters parked in the lane's own E entries, then loaded
 #pragma unroll 1
         for (int r = 0; r < K; ++r) {
-            const int i = r0 + t * K + r;
+            const int i = base + r;
             const int ic = min(i, mload - 1);
             const RowPar p = load_row(pb, lin, ro + ic, c_prob);
-            const double bn = load_beta(pb, lin, ro + min(i + 1, mload - 1), c_prob);
             const bool real = i < m;
-            *slot(0, r) = real ? (T)p.a : (T)0;
-            *slot(1, r) = real ? (T)p.b : (T)0;
-            *slot(2, r) = real ? (T)p.d : (i == m ? (T)1 : (T)0);
-            *slot(3, r) = real ? (T)p.e : (T)1;
-            *slot(4, r) = (real && i + 1 < m) ? (T)(bn * p.z) : (T)0;
+            if constexpr (HAT) {
+                const bool inner = real && i >= 1;
+                const double bn = i + 1 < m ? load_beta(pb, lin, ro + i + 1, c_prob) : 1.0;
+                const double zp = inner ? load_row(pb, lin, ro + i - 1, c_prob).z : 0.0;
+                const bool ok = p.b >= 0x1p-20;
+                bad = bad || (inner && !ok);
+                *slot(0, r) = i == 0 ? (T)0 : real ? (T)p.a : (i == m ? (T)1 : (T)0);
+                *slot(1, r) = inner ? (T)(p.b * zp) : (T)0;
+                *slot(2, r) = inner ? (T)(bn * p.d) : (T)0;
+                *slot(3, r) = (inner && ok) ? (T)(bn * p.e / p.b) : (T)0;
+                *slot(4, r) = real ? (T)p.e : (i == m ? (T)1 : (T)0);
+            } else {
+                const double bn = load_beta(pb, lin, ro + min(i + 1, mload - 1), c_prob);
+                *slot(0, r) = real ? (T)p.a : (T)0;
+                *slot(1, r) = real ? (T)p.b : (T)0;
+                *slot(2, r) = real ? (T)p.d : (i == m ? (T)1 : (T)0);
+                *slot(3, r) = real ? (T)p.e : (T)1;
+                *slot(4, r) = (real && i + 1 < m) ? (T)(bn * p.z) : (T)0;
+            }
         }
 #pragma unroll
         for (int r = 0; r < K; ++r) {
-            al[r] = *slot(0, r);
-            be[r] = *slot(1, r);
-            de[r] = *slot(2, r);
-            ep[r] = *slot(3, r);
-            zt[r] = *slot(4, r);
+            if constexpr (HAT) {
+                al[r] = *slot(0, r);
+                cd[r] = *slot(1, r);
+                kd[r] = *slot(2, r);
+                ke[r] = *slot(3, r);
+                ep[r] = *slot(4, r);
+            } else {
+                al[r] = *slot(0, r);
+                be[r] = *slot(1, r);
+                de[r] = *slot(2, r);
+                ep[r] = *slot(3, r);
+                zt[r] = *slot(4, r);
+            }
         }
         if (t == 0 && m > 0 && r0 == 0) edge = (T)(ldexp(load_beta(pb, lin, ro, c_prob), Range<T>::kExp) / (double)n);
         // E[c][row] = lam of the row against haplotype code c (N matches all, PAD = 0)
 #pragma unroll 1
         for (int r = 0; r < C::KP; ++r) {
-            const int i = r0 + t * K + r;
+            const int i = base + r;
             const int ic = min(i, mload - 1);
             const RowPar p = load_row(pb, lin, ro + ic, c_prob);
             const bool real = (r < K) && (i < m);
+            const bool one = HAT && (r < K) && (i == m);
             const uint32_t code = clamp_code(pb.read_bases[ro + ic]);
             const T lm = real ? (T)p.lm : (T)0, lx = real ? (T)p.lx : (T)0;
 #pragma unroll
             for (int c = 0; c < kCodes; ++c) {
                 const bool match = code == (uint32_t)c || code == 4u || c == 4;
-                *slot(c, r) = c == kPad ? (T)0 : (match ? lm : lx);
+                *slot(c, r) = one ? (T)1 : c == kPad ? (T)0 : (match ? lm : lx);
             }
         }
     }
-    // The first lane of a group takes the row above its first row from the
-    // boundary of the DP (row 0: M = I = 0, D = 1/n), but in groups of 4 or 8
-    // lanes the lane shift hands it the previous group's last row instead.
-    // That row is an absorbing row (rows past m: M = 0 and D = 0 exactly), so
-    // its M and D terms vanish by themselves; its I enters the first row only
-    // through beta (with the diagonal) and eps (from above), and both are set
-    // to 0 here, which is exact because row 0 has I = 0.  In later windows of
-    // a long read the row above is a real stored row and keeps its terms.
+    // Plain states: the first lane of a group takes the row above its first
+    // row from the boundary of the DP (row 0: M = I = 0, D = 1/n), but in
+    // groups of 4 or 8 lanes the lane shift hands it the previous group's last
+    // row instead.  That row is an absorbing row (rows past m: M = 0 and D = 0
+    // exactly), so its M and D terms vanish by themselves; its I enters the
+    // first row only through beta (with the diagonal) and eps (from above),
+    // and both are set to 0 here, which is exact because row 0 has I = 0.  In
+    // later windows of a long read the row above is a real stored row and
+    // keeps its terms.  (Rescaled states: the read's first row has zero
+    // coefficients on every received value but the Ih diagonal, and that one
+    // is exactly zero in the previous group's last row.)
     T epI0 = ep[0];
-    if (t == 0 && r0 == 0) {
-        be[0] = 0;
-        epI0 = 0;
+    if constexpr (!HAT) {
+        if (t == 0 && r0 == 0) {
+            be[0] = 0;
+            epI0 = 0;
+        }
+    }
+    // rescaled states: the pair goes to the FP64 sweep if any of its rows has
+    // a beta below 2^-20 (rows of earlier windows are checked by the final one)
+    bool gbad = false;
+    if constexpr (HAT) {
+        if constexpr (W) {
+            if (fin)
+                for (int i = 1 + t; i < r0; i += 64) bad = bad || beta_tiny(pb, lin, ro + i);
+        }
+        const uint64_t bm = __ballot(bad);
+        const uint64_t gm = P == 64 ? ~0ull : (((1ull << P) - 1) << (g * P));
+        gbad = (bm & gm) != 0;
     }
     // haplotype ring: PAD everywhere (negative columns read slot 3), then chunks 0 and 1
     for (int x = t; x < kRingAlloc; x += P) ring[x] = (uint16_t)(kPad * C::CODE_BYTES);
     __syncthreads();
-    ring_fill<P>(ring, 0, hap, n, t, C::CODE_BYTES);
-    ring_fill<P>(ring, 1, hap, n, t, C::CODE_BYTES);
+    {
+        uint32_t c0[kChunk / P], c1[kChunk / P];
+        ring_load<P>(c0, 0, hap, n, t);
+        ring_load<P>(c1, 1, hap, n, t);
+        ring_store<P>(ring, 0, c0, t, C::CODE_BYTES);
+        ring_store<P>(ring, 1, c1, t, C::CODE_BYTES);
+    }
+    __syncthreads();
 
     // ---- sweep ----------------------------------------------------------------
     T M[K], I[K], D[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) M[r] = I[r] = D[r] = 0;
-    T Md = 0, Id = 0, Dd = edge;  // row above the lane's first row, column j-1
-    double acc = 0.0;          // row-m sum (Viterbi: maximum); each 64-step chunk in T first
+    // row above the lane's first row at column j-1 = 0: the first lane's
+    // row-0 boundary (the edge value) sits in Ih (rescaled) or Dt (plain)
+    T Md = 0, Id = HAT ? edge : (T)0, Dd = HAT ? (T)0 : edge;
+    // row-m sum (Viterbi: maximum).  Plain states: each 64-step chunk in T,
+    // then FP64.  Rescaled states: the absorbing row's Dh, flushed into FP64
+    // every 64 steps by the lane that holds it (row index rml).
+    double acc = 0.0;
+    const int rml = m - base;
     // steps run in pairs; a step past the last column only meets PAD columns
-    // in the last lane and adds exact zeros
-    const int total = (nmax + P - 1 + 1) & ~1;
+    // in the last lane and adds exact zeros.  The last lane reaches column
+    // nmax after nmax + P - 1 steps.  With the rescaled states the absorbing
+    // row (possibly in the last lane) sums column n's (M + I) as its M at
+    // column n + 1 into its Dh at column n + 2: every lane runs to column
+    // n + 2 at least, so that this last term always takes the same FP32 path
+    // whatever the other pairs of the tile (its M at the last step is then
+    // exactly zero).
+    const int total = HAT ? (nmax + P + 2) & ~1 : (nmax + P) & ~1;
     const char *ebase_lane = E + lane * 8;
 
     for (int s0 = 0; s0 < total; s0 += kChunk) {
-        ring_fill<P>(ring, s0 / kChunk + 2, hap, n, t, C::CODE_BYTES);
+        uint32_t ahead[kChunk / P];
+        ring_load<P>(ahead, s0 / kChunk + 2, hap, n, t);
         if constexpr (W) {
             // lane t stages the boundary row at column s0 + 1 + t, which
-            // lane 0 takes at step s0 + t (zero in window 0: the row-0 D
-            // comes from `edge`)
+            // lane 0 takes at step s0 + t (zero in window 0: the row-0
+            // boundary comes from `edge`)
             const int j = s0 + 1 + t;
             T v0 = 0, v1 = 0, v2 = 0;
             if (r0 > 0 && j <= n) {
@@ -413,42 +607,73 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             top[t] = v0;
             top[64 + t] = v1;
             top[128 + t] = v2;
+            __syncthreads();
         }
-        __syncthreads();
         const uint16_t *hp = ring + ((s0 - t) & (kRing - 1));
         const int cnt = min(kChunk, total - s0);
         T la[C::KP], lb[C::KP];
-        T part = 0;
         load_lam<T, P, K>(la, ebase_lane + hp[0]);
-        for (int u = 0; u < cnt; u += 2) {
-            load_lam<T, P, K>(lb, ebase_lane + hp[u + 1]);
-            if constexpr (W) {
-                window_step<T, K, V>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, epI0, edge, part, top, u, t,
-                                     fin, bnd, s0 + u, n);
-                load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
-                window_step<T, K, V>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, epI0, edge, part, top, u + 1,
-                                     t, fin, bnd, s0 + u + 1, n);
-            } else {
-                cell_step<T, P, K, false, V>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, epI0, edge, part);
-                load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
-                cell_step<T, P, K, false, V>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, epI0, edge, part);
+        if constexpr (HAT) {
+            for (int u = 0; u < cnt; u += 2) {
+                load_lam<T, P, K>(lb, ebase_lane + hp[u + 1]);
+                if constexpr (W) {
+                    window_step_hat<T, K, V>(M, I, D, Md, Id, Dd, la, al, cd, kd, ke, ep, edge, top, u, t, fin,
+                                             bnd, s0 + u, n);
+                    load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
+                    window_step_hat<T, K, V>(M, I, D, Md, Id, Dd, lb, al, cd, kd, ke, ep, edge, top, u + 1, t,
+                                             fin, bnd, s0 + u + 1, n);
+                } else {
+                    cell_step_hat<T, P, K, false, V>(M, I, D, Md, Id, Dd, la, al, cd, kd, ke, ep, edge);
+                    load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
+                    cell_step_hat<T, P, K, false, V>(M, I, D, Md, Id, Dd, lb, al, cd, kd, ke, ep, edge);
+                }
             }
+            // the absorbing row's Dh (Viterbi: its running maximum) moves
+            // into the FP64 accumulator; nothing else reads it
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                if (r == rml) {
+                    if constexpr (V)
+                        acc = fmax(acc, (double)D[r]);
+                    else
+                        acc += (double)D[r];
+                    D[r] = 0;
+                }
+            }
+        } else {
+            T part = 0;
+            for (int u = 0; u < cnt; u += 2) {
+                load_lam<T, P, K>(lb, ebase_lane + hp[u + 1]);
+                if constexpr (W) {
+                    window_step<T, K, V>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, epI0, edge, part, top, u, t,
+                                         fin, bnd, s0 + u, n);
+                    load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
+                    window_step<T, K, V>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, epI0, edge, part, top, u + 1,
+                                         t, fin, bnd, s0 + u + 1, n);
+                } else {
+                    cell_step<T, P, K, false, V>(M, I, D, Md, Id, Dd, la, al, be, de, ep, zt, epI0, edge, part);
+                    load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
+                    cell_step<T, P, K, false, V>(M, I, D, Md, Id, Dd, lb, al, be, de, ep, zt, epI0, edge, part);
+                }
+            }
+            if constexpr (V)
+                acc = fmax(acc, (double)part);
+            else
+                acc += (double)part;
         }
-        if constexpr (V)
-            acc = fmax(acc, (double)part);
-        else
-            acc += (double)part;
+        ring_store<P>(ring, s0 / kChunk + 2, ahead, t, C::CODE_BYTES);
         __syncthreads();
     }
 
-    // ---- epilogue: the group's last lane owns the row-m sum ------------------
-    if (gvalid && t == P - 1 && fin) {
+    // ---- epilogue: the lane that holds the row-m sum writes it ---------------
+    const bool owner = HAT ? (rml >= 0 && rml < K) : (t == P - 1);
+    if (gvalid && owner && fin) {
         const double lg = log10(acc) - (double)Range<T>::kExp * 0.30102999566398119521;
         A.out_log10[rec.out] = lg;
         if (A.mode == kModeRescue) {
             if (A.out_status) A.out_status[rec.out] = (acc >= A.floor64) ? 1 : 2;
         } else {
-            const bool ok = (acc >= A.threshold) && (acc <= 3.0e38);
+            const bool ok = !gbad && (acc >= A.threshold) && (acc <= 3.0e38);
             if (A.mode == kModeBinned && !ok) {
                 if (W) {
                     const int slot = atomicAdd(&A.book->long_rescue_count, 1);

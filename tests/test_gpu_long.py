@@ -76,3 +76,24 @@ def test_long_reads_explicit_params_and_replay():
     assert np.array_equal(s1, st2.cpu().numpy())
     plan.close()
     check_against_oracle(prob, a1, s1, log10_params=lg)
+
+
+def test_long_read_gap_continuation_zero_in_an_earlier_window():
+    """Gap-continuation Phred 0 (beta = 0) on a row of the first window of a
+    long read: the FP32 windowed sweep's final window must still send the
+    pair to the FP64 sweep, and no other pair changes status."""
+    prob = long_problem()
+    got0, st0 = gpu_forward(prob)
+    r_idx, _ = prob.pair_index()
+    m_all = np.diff(prob.read_offset)
+    cand = [r for r in range(prob.num_reads) if m_all[r] > 1024 and np.any(st0[r_idx == r] == binding.PAIR_FP32)]
+    assert cand, "no long read with a pair finished in FP32"
+    r = cand[0]
+    prob.gcp_qual[prob.read_offset[r] + 300] = 0
+    mine = r_idx == r
+    say(f"long read {r} (m = {m_all[r]}): Phred 0 on row 300, {int((st0[mine] == 0).sum())} FP32 pairs before")
+    got, st = gpu_forward(prob)
+    check_against_oracle(prob, got, st)
+    assert np.all(st[mine] != binding.PAIR_FP32)
+    assert np.all(st[mine & (st0 == binding.PAIR_FP32)] == binding.PAIR_FP64)
+    assert np.array_equal(st[~mine], st0[~mine])

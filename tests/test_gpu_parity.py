@@ -65,6 +65,79 @@ def test_small_lane_groups_ragged(force_p):
     plan.close()
 
 
+@pytest.mark.parametrize("force_p", [4, 8, 16, 32, 64])
+def test_read_ending_at_haplotype_end(force_p):
+    """Reads copied from the end of their haplotype put most of L in the last
+    column, and reads of P K - 1 bases put the absorbing row in the group's
+    last lane, which must still see column n + 1 (where the rescaled FP32
+    states collect the last column).  Odd and even n + P, forward and
+    Viterbi, one batch per (K, n) so that tiles hold one haplotype length."""
+    say(f"reads at the haplotype end, P={force_p}")
+    rng = np.random.default_rng(50 + force_p)
+    ks = (4, 6) if force_p == 32 else (2, 3, 5)
+    batches = []
+    for k in ks:
+        m = force_p * k - 1
+        for n in (m, m + 3, m + 4, m + 11):
+            hap = rng.choice(list("ACGT"), size=n)
+            reads = ["".join(hap[n - m:])]
+            for _ in range(3):  # the same suffix with a few substitutions
+                r = hap[n - m:].copy()
+                flip = rng.random(m) < 0.02
+                r[flip] = rng.choice(list("ACGT"), size=int(flip.sum()))
+                reads.append("".join(r))
+            batches.append((reads, ["".join(hap)]))
+    prob = wl.from_strings(batches)
+    prob.base_qual[:] = rng.integers(10, 41, size=len(prob.base_qual))
+    prob.gcp_qual[:] = rng.integers(5, 20, size=len(prob.gcp_qual))
+    got, st = gpu_forward(prob, force_p=force_p)
+    check_against_oracle(prob, got, st)
+    assert np.all(st == binding.PAIR_FP32)
+    import torch
+    dev = binding.DeviceProblem(prob)
+    plan = binding.Plan(prob, force_p=force_p)
+    v, sv = plan.viterbi(dev)
+    torch.cuda.synchronize()
+    check_against_oracle(prob, v.cpu().numpy(), sv.cpu().numpy(), ref=oracle.viterbi(prob))
+    plan.close()
+
+
+def test_result_independent_of_tile_partners():
+    """A pair's FP32 result is bit-identical whatever pairs share its tile:
+    a second batch of reads of the same lengths against slightly longer
+    haplotypes lands in the same bins and haplotype-length buckets, which
+    changes the tiles' haplotype lengths and step counts."""
+    say("results independent of tile partners")
+    rng = np.random.default_rng(60)
+    ms, ns1, ns2 = [40, 47, 100, 180, 223], [60, 300], [61, 62, 301, 302, 370]
+    ref = rng.choice(list("ACGT"), size=400)
+    haps1 = ["".join(ref[:n]) for n in ns1]
+    haps2 = ["".join(ref[:n]) for n in ns2]
+    reads = []
+    for m in ms:
+        s0 = int(rng.integers(0, 60 - m + 1)) if m < 60 else int(rng.integers(0, 300 - m + 1))
+        r = ref[s0:s0 + m].copy()
+        err = rng.random(m) < 0.02
+        r[err] = rng.choice(list("ACGT"), size=int(err.sum()))
+        reads.append("".join(r))
+    a = wl.from_strings([(reads, haps1)])
+    b = wl.from_strings([(reads, haps1), (reads, haps2)])
+    nb = len(a.base_qual)
+    for f in ("base_qual", "ins_qual", "del_qual", "gcp_qual"):
+        lo, hi = {"base_qual": (10, 41), "ins_qual": (30, 46), "del_qual": (30, 46), "gcp_qual": (5, 20)}[f]
+        q = rng.integers(lo, hi, size=len(getattr(b, f))).astype(np.uint8)
+        getattr(b, f)[:] = q
+        getattr(a, f)[:] = q[:nb]
+    for kw in (dict(), dict(force_p=64)):
+        ga, sa = gpu_forward(a, **kw)
+        gb, sb = gpu_forward(b, **kw)
+        k = a.num_pairs
+        assert np.array_equal(sa, sb[:k]) and (sa == binding.PAIR_FP32).sum() >= 6, (sa, sb[:k])
+        diff = np.nonzero(ga.view(np.int64) != gb[:k].view(np.int64))[0]
+        assert len(diff) == 0, (kw, diff, ga[diff], gb[diff])
+    check_against_oracle(b, gb, sb)
+
+
 def _ragged(seed, lens_m, lens_n, related=True):
     """Batches with the given read and haplotype lengths.  related=True makes
     haplotypes mutated copies of one reference and reads error-bearing
@@ -120,6 +193,39 @@ def test_ragged_lengths_every_bin():
     for kw in (dict(), dict(use_graph=False), dict(force_p=64, use_graph=False)):
         got, st = gpu_forward(prob, **kw)
         check_against_oracle(prob, got, st, ref=ref)
+
+
+def test_gap_continuation_zero_rows():
+    """Gap-continuation Phred 0 (eps = 1, beta = 0) on a row below the
+    first: the FP32 sweep's rescaled insertion state (beta of the next row
+    times I) cannot carry that row, so exactly those pairs are recomputed by
+    the FP64 sweep; Phred 1..4 (beta down to 0.21) stays in FP32.  Rows at
+    both ends of the read and inside, in the default groups and in 64-lane
+    groups."""
+    say("gap continuation Phred 0")
+    prob = _ragged(41, [[20, 60, 150, 300, 63], [100, 700, 255, 31]], [[80, 200], [150, 900, 60]])
+    rng = np.random.default_rng(42)
+    m_all = prob.read_lengths
+    zero_rows = {0: [5], 1: [59], 3: [1, 150], 6: [699], 8: [30]}  # read -> rows with Phred 0
+    for r, rows in zero_rows.items():
+        for i in rows:
+            assert 1 <= i < m_all[r]
+            prob.gcp_qual[prob.read_offset[r] + i] = 0
+    for r in (2, 5):  # Phred 1..4 on every row
+        a, b = prob.read_offset[r], prob.read_offset[r + 1]
+        prob.gcp_qual[a:b] = rng.integers(1, 5, size=b - a)
+    ref = oracle.forward(prob)
+    r_idx, _ = prob.pair_index()
+    zero = np.isin(r_idx, list(zero_rows))
+    inside = ref > -60.0  # well inside the FP32 range (rescue below about -64.1)
+    say(f"  {int((zero & inside).sum())} flagged and {int((~zero & inside).sum())} plain pairs in range")
+    assert (zero & inside).sum() >= 6 and (~zero & inside).sum() >= 6
+    for kw in (dict(), dict(force_p=64, use_graph=False)):
+        got, st = gpu_forward(prob, **kw)
+        check_against_oracle(prob, got, st, ref=ref)
+        assert np.all(st[zero] != binding.PAIR_FP32), st[zero]
+        assert np.all(st[zero & inside] == binding.PAIR_FP64), st[zero & inside]
+        assert np.all(st[~zero & inside] == binding.PAIR_FP32), st[~zero & inside]
 
 
 def test_fp64_floor_status():
