@@ -449,7 +449,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
                     al[r] = i == 0 ? (T)0 : real ? (T)(1.0f - d - z) : (i == m ? (T)1 : (T)0);
                     cd[r] = inner ? (T)(b * c_pf[dq[r]]) : (T)0;
                     kd[r] = inner ? (T)(bn * d) : (T)0;
-                    ke[r] = (inner && ok) ? (T)(bn * e / b) : (T)0;
+                    ke[r] = (inner && ok) ? (T)(bn * e * __builtin_amdgcn_rcpf(b)) : (T)0;
                     ep[r] = real ? (T)e : (i == m ? (T)1 : (T)0);
                 } else {
                     al[r] = real ? (T)(1.0f - d - z) : (T)0;
@@ -459,7 +459,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
                     zt[r] = (real && i + 1 < m) ? (T)(c_1mpf[gq[r + 1]] * z) : (T)0;
                 }
             }
-            if (t == 0 && m > 0 && r0 == 0) edge = (T)(ldexp((double)c_1mpf[gq[0]], Range<T>::kExp) / (double)n);
+            if (t == 0 && m > 0 && r0 == 0) edge = ldexpf(c_1mpf[gq[0]], Range<T>::kExp) / (float)n;
         }
     } else {
         // FP64 sweep or explicit parameters: one row at a time in FP64, the
@@ -630,16 +630,16 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             }
             // the absorbing row's Dh (Viterbi: its running maximum) moves
             // into the FP64 accumulator; nothing else reads it
+            T dm = 0;
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                if (r == rml) {
-                    if constexpr (V)
-                        acc = fmax(acc, (double)D[r]);
-                    else
-                        acc += (double)D[r];
-                    D[r] = 0;
-                }
+                dm = r == rml ? D[r] : dm;
+                D[r] = r == rml ? (T)0 : D[r];
             }
+            if constexpr (V)
+                acc = fmax(acc, (double)dm);
+            else
+                acc += (double)dm;
         } else {
             T part = 0;
             for (int u = 0; u < cnt; u += 2) {
