@@ -717,7 +717,13 @@ bool fwd32_supported(int P, int K)
 // the next tile (one read/haplotype pair per lane group) from the bin's
 // cursor.  Records of a bin are ordered longest haplotype first.
 // waves per SIMD each configuration should reach (register budget 512 / W)
-constexpr int waves_for(int K) { return K <= 6 ? 4 : K <= 10 ? 3 : 2; }
+#ifndef PH_W4_MAX_K
+#define PH_W4_MAX_K 6
+#endif
+#ifndef PH_W3_MAX_K
+#define PH_W3_MAX_K 10
+#endif
+constexpr int waves_for(int K) { return K <= PH_W4_MAX_K ? 4 : K <= PH_W3_MAX_K ? 3 : 2; }
 // the max-product cell keeps more temporaries live (no FMA contraction)
 constexpr int waves_for_viterbi(int K) { return K <= 5 ? 4 : K <= 8 ? 3 : 2; }
 
