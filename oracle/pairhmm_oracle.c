@@ -375,7 +375,7 @@ int oracle_backward(int m, int n, const uint8_t *r, const uint8_t *h, const doub
 }
 
 /* ------------------------------------------------------------------------
- * Batch driver: every pair of every batch, in output order (batch-major,
+ * Batch loop: every pair of every batch, in output order (batch-major,
  * then read, then haplotype), spread over a pool of threads.  Parameters
  * come from Phred bytes, or from explicit log10 parameters [sum m x 7] when
  * log10_par is non-NULL.

@@ -254,8 +254,8 @@ def test_gradients_central_fd():
             assert fd == pytest.approx(g[i, c], abs=1e-7), (i, c)
 
 
-# --- batch driver -------------------------------------------------------------------
-def test_batch_driver_matches_single_pairs():
+# --- batch loop ---------------------------------------------------------------------
+def test_batch_loop_matches_single_pairs():
     prob = wl.config0()
     out, used = oracle.forward(prob, return_threads=True)
     assert used >= 1 and len(out) == prob.num_pairs == 32
@@ -339,8 +339,8 @@ def test_viterbi_ungapped_max_scan_150x300():
     assert oracle.viterbi_pair(r, h, p) == pytest.approx(want, abs=1e-11)
 
 
-def test_viterbi_rescaling_and_batch_driver():
-    """Row rescaling leaves in-range scores unchanged, and the batch driver
+def test_viterbi_rescaling_and_batch_loop():
+    """Row rescaling leaves in-range scores unchanged, and the batch loop
     equals the single-pair calls (Phred and explicit parameters)."""
     prob = wl.config0()
     r_idx, h_idx = prob.pair_index()
