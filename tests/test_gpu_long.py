@@ -97,3 +97,32 @@ def test_long_read_gap_continuation_zero_in_an_earlier_window():
     assert np.all(st[mine] != binding.PAIR_FP32)
     assert np.all(st[mine & (st0 == binding.PAIR_FP32)] == binding.PAIR_FP64)
     assert np.array_equal(st[~mine], st0[~mine])
+
+
+def test_maximum_read_length():
+    """A read of 65,535 bases (the longest the plan takes: 64 windows of 1,024
+    rows) against haplotypes of 1,000 and 1,700 bases, in explicit-parameter
+    mode with a gap continuation of 1 - 2^-13 (exact in FP32, so that 64,535
+    insertion rows do not compound a rounding of the parameter), which keeps
+    the likelihood inside the FP32 range; against the oracle."""
+    rng = np.random.default_rng(25)
+    m = 65535
+    hap = rng.choice(list("ACGT"), size=1700)
+    read = np.concatenate([hap[:1000], rng.choice(list("ACGT"), size=m - 1000)])
+    prob = wl.from_strings([(["".join(read)], ["".join(hap[:1000]), "".join(hap)])])
+    par = np.empty((m, 7))
+    eps, delta, zeta, q = 1 - 2.0 ** -13, 0.1, 1e-4, 1e-3
+    par[:, 0] = 1 - delta - zeta
+    par[:, 1] = 1 - eps
+    par[:, 2] = delta
+    par[:, 3] = eps
+    par[:, 4] = zeta
+    par[:, 5] = 1 - q
+    par[:, 6] = q / 3
+    lg = np.log10(par).astype(np.float32)
+    say(f"maximum read length {m}: {prob.num_pairs} pairs")
+    got, st = gpu_forward(prob, log10_params=lg)
+    ref = oracle.forward(prob, log10_params=lg)
+    say(f"  log10 L {ref}, statuses {st}")
+    assert np.all(np.isfinite(ref))
+    check_against_oracle(prob, got, st, ref=ref)

@@ -322,6 +322,35 @@ def test_config1_full_size_sampled():
     check_against_oracle(prob, got, st, pairs=idx)
 
 
+def test_config2_full_size_sampled():
+    """The benchmark's mixed batch at full size (2,000 regions, 3,757,266
+    pairs) through the default plan (autotuned bins, per-bin launches, graph),
+    2,000 seeded sampled pairs checked one by one against the oracle."""
+    say("config2 full size, sampled")
+    prob = wl.config2()
+    got, st = gpu_forward(prob)
+    idx = np.sort(np.random.default_rng(7).choice(prob.num_pairs, 2000, replace=False))
+    check_against_oracle(prob, got, st, pairs=idx)
+    assert np.all(st == binding.PAIR_FP32)
+
+
+def test_config3_full_size_sampled():
+    """The precision-stress set at full size (50,000 pairs, 250 bp reads with
+    N bases and low qualities against 1,000-5,000 bp divergent haplotypes):
+    most pairs take the FP64 rescue; 400 seeded sampled pairs of each path
+    checked against the oracle."""
+    say("config3 full size, sampled")
+    prob = wl.config3()
+    got, st = gpu_forward(prob)
+    rng = np.random.default_rng(8)
+    idx = []
+    for code in (binding.PAIR_FP32, binding.PAIR_FP64):
+        cand = np.nonzero(st == code)[0]
+        assert len(cand) >= 400, (code, len(cand))
+        idx.append(rng.choice(cand, 400, replace=False))
+    check_against_oracle(prob, got, st, pairs=np.sort(np.concatenate(idx)))
+
+
 def test_rescue_path_config3_subset():
     say("config3 subset: FP32 + FP64 rescue")
     prob = wl.config3(pairs=300)
