@@ -2,7 +2,9 @@
 //
 // The paper computes only the forward likelihood (arXiv 2411.11547,
 // Section II-A, Eq. 1-4).  Its derivatives follow from the same DP run
-// backwards.  The state carried here is (M, I, D') with D' = beta_{i+1} D,
+// backwards.  The FP32 pass carries the forward sweep's rescaled states
+// (M, Ih, Dh), whose recurrences and reverse recurrences are given with
+// adj_backward below; the FP64 pass carries (M, I, D') with D' = beta_{i+1} D,
 // D' = zeta'_i M(i,j-1) + eps_i D'(i,j-1), zeta'_i = beta_{i+1} zeta_i, so
 // that M(i,j) = lam_ij (alpha_i M + beta_i I + D')(i-1,j-1).  With
 // B_X(i,j) = dL/dX(i,j) and B(m,.) seeded by the result formula
@@ -126,21 +128,34 @@ struct AdjCfg {
 };
 
 // Per-pair state shared by the forward and backward parts: the record, the
-// per-row parameters of the lane's K rows (absorbing rows past the read end,
+// per-row coefficients of the lane's K rows (absorbing rows past the read end,
 // as in the forward sweep), the (lam, w) table and the haplotype staged in
 // LDS with PAD outside columns 1..n.
+//
+// FP32 (HAT): the forward's rescaled states Ih = beta_{i+1} I and
+// Dh = D / zeta_i, with al = alpha, cd = beta_i zeta_{i-1}, kd = beta_{i+1}
+// delta_i, ke = beta_{i+1} eps_i / beta_i, ep = eps (beta after the last read
+// row read as 1; the read's first row has al = cd = kd = ke = 0, its boundary
+// D entering as the edge value through Ih).  The absorbing row m + 1 has
+// lam = al = ep = 1 and sums the last read row's M + I along its Dh; rows
+// past it are zero.  A row with beta below 2^-20 sends the pair to FP64.
+// FP64: D carried as D' = beta_{i+1} D, al, be, de, ep as Eq. (1)-(3) and
+// ze = beta_{i+1} zeta_i, the absorbing rows passing I down to the group's
+// last lane.
 template <typename T, int P, int K>
 struct AdjPair {
+    static constexpr bool HAT = sizeof(T) == 4;
     using C = AdjCfg<T, P, K>;
     using V2 = typename Pair2<T>::V;
     int lane, g, t;
     AdjRec rec;
     int64_t ro;
     int m, n, S;
-    // ze holds zeta' = beta_{i+1} zeta_i: D is carried pre-multiplied by the
-    // next row's beta, D' = beta_{i+1} D, so that beta (I + D) in Eq. (1)
-    // costs one FMA (the last real row's D' is 0: nothing follows it)
-    T al[K], be[K], de[K], ep[K], ze[K];
+    int rml;     // the absorbing row's index among the lane's rows (HAT; out of 0..K-1 elsewhere)
+    bool bad;    // HAT: one of the lane's rows has beta below 2^-20
+    T edge;      // the read's first row's boundary D (scaled), first lane only
+    T al[K], be[K], de[K], ep[K], ze[K];  // plain states (be, de, ze unused with HAT)
+    T cd[K], kd[K], ke[K];                // rescaled states
     char *E;
     const char *El;      // the lane's column of the (lam, w) table
     const uint16_t *hs;  // staged byte offsets of the table of each column's code; column j at hs[j + P]
@@ -158,6 +173,8 @@ struct AdjPair {
         ro = pb.read_offset[rec.read];
         m = (int)(pb.read_offset[rec.read + 1] - ro);
         n = rec.n;
+        rml = m - t * K;
+        bad = false;
         E = lds;
         char *mine = E + lane * C::ENT;
         auto slot = [&](int c, int r) -> T * { return (T *)(mine + c * C::CODE_BYTES + r * C::ROW_BYTES); };
@@ -167,33 +184,58 @@ struct AdjPair {
             const int ic = min(i, m - 1);
             const RowPar p = load_row(pb, A.lin_params, ro + ic, c_prob);
             const bool real = i < m;
-            *slot(0, r) = real ? (T)p.a : (T)0;
-            *slot(1, r) = real ? (T)p.b : (T)0;
-            *slot(2, r) = real ? (T)p.d : (i == m ? (T)1 : (T)0);
-            *slot(3, r) = real ? (T)p.e : (T)1;
-            const double bnext = (i + 1 < m) ? load_beta(pb, A.lin_params, ro + i + 1, c_prob) : 0.0;
-            *slot(4, r) = real ? (T)(p.z * bnext) : (T)0;
+            if constexpr (HAT) {
+                const bool inner = real && i >= 1;
+                const double bn = (i + 1 < m) ? load_beta(pb, A.lin_params, ro + i + 1, c_prob) : 1.0;
+                const double zp = inner ? load_row(pb, A.lin_params, ro + i - 1, c_prob).z : 0.0;
+                const bool ok = p.b >= 0x1p-20;
+                bad = bad || (inner && !ok);
+                *slot(0, r) = i == 0 ? (T)0 : real ? (T)p.a : (i == m ? (T)1 : (T)0);
+                *slot(1, r) = inner ? (T)(p.b * zp) : (T)0;
+                *slot(2, r) = inner ? (T)(bn * p.d) : (T)0;
+                *slot(3, r) = (inner && ok) ? (T)(bn * p.e / p.b) : (T)0;
+                *slot(4, r) = real ? (T)p.e : (i == m ? (T)1 : (T)0);
+            } else {
+                *slot(0, r) = real ? (T)p.a : (T)0;
+                *slot(1, r) = real ? (T)p.b : (T)0;
+                *slot(2, r) = real ? (T)p.d : (i == m ? (T)1 : (T)0);
+                *slot(3, r) = real ? (T)p.e : (T)1;
+                const double bnext = (i + 1 < m) ? load_beta(pb, A.lin_params, ro + i + 1, c_prob) : 0.0;
+                *slot(4, r) = real ? (T)(p.z * bnext) : (T)0;
+            }
         }
 #pragma unroll
         for (int r = 0; r < K; ++r) {
-            al[r] = *slot(0, r);
-            be[r] = *slot(1, r);
-            de[r] = *slot(2, r);
-            ep[r] = *slot(3, r);
-            ze[r] = *slot(4, r);
+            if constexpr (HAT) {
+                al[r] = *slot(0, r);
+                cd[r] = *slot(1, r);
+                kd[r] = *slot(2, r);
+                ke[r] = *slot(3, r);
+                ep[r] = *slot(4, r);
+            } else {
+                al[r] = *slot(0, r);
+                be[r] = *slot(1, r);
+                de[r] = *slot(2, r);
+                ep[r] = *slot(3, r);
+                ze[r] = *slot(4, r);
+            }
         }
+        // D(0, j) = 1/n times the first read row's beta (it multiplies that
+        // D in both forms), scaled
+        edge = (t == 0) ? (T)(ldexp(load_beta(pb, A.lin_params, ro, c_prob), AdjRange<T>::kFwd) / (double)n) : (T)0;
 #pragma unroll 1
         for (int r = 0; r < K; ++r) {
             const int i = t * K + r;
             const int ic = min(i, m - 1);
             const RowPar p = load_row(pb, A.lin_params, ro + ic, c_prob);
             const bool real = i < m;
+            const bool one = HAT && i == m;  // the absorbing row takes every column with lam = 1
             const uint32_t code = clamp_code(pb.read_bases[ro + ic]);
 #pragma unroll
             for (int c = 0; c < kCodes; ++c) {
                 const bool match = code == (uint32_t)c || code == 4u || c == 4;
                 V2 v;
-                v.x = (T)0;
+                v.x = one ? (T)1 : (T)0;
                 v.y = (T)0;
                 if (real && c != kPad) {
                     v.x = match ? (T)p.lm : (T)p.lx;
@@ -216,30 +258,44 @@ struct AdjPair {
     }
 
     __device__ __forceinline__ const char *ecol(int s) const { return El + hs[s - t + 1 + P]; }
-
-    // D'(0, j) = beta_1 / n, scaled: the first lane's row-0 boundary
-    __device__ __forceinline__ T edge() const
-    {
-        return (t == 0) ? (T)(ldexp((double)be[0], AdjRange<T>::kFwd) / (double)n) : (T)0;
-    }
 };
 
-// One forward step of the lane's K rows in the plain formulation of
-// Eq. (1)-(3) (D kept unscaled, as the gradients need it): (mo, io, do_)
-// hold column j-1 on entry, (mn, in, dn) receive column j; (mu, iu) and
-// (md, id, dd) are the row above at columns j and j-1.
-template <typename T, int K>
-__device__ __forceinline__ void adj_cell_step(const T (&mo)[K], const T (&io)[K], const T (&do_)[K], T (&mn)[K],
-                                              T (&in)[K], T (&dn)[K], T mu, T iu, T md, T id, T dd, const T *lam,
-                                              const T (&al)[K], const T (&be)[K], const T (&de)[K],
-                                              const T (&ep)[K], const T (&ze)[K])
+// Lane t receives lane t-1's value.  With the rescaled states (FP32) a
+// 32-lane group's first lane may take the previous group's last row from a
+// single wave shift: that row is the absorbing row or past it (Ih exactly
+// zero, M and Dh only meeting zero coefficients), so one DPP move serves
+// every group size.
+template <typename T, int P>
+__device__ __forceinline__ T adj_up(T v)
+{
+    if constexpr (sizeof(T) == 4 && P == 32)
+        return __builtin_bit_cast(
+            float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138 /* wave_shr:1 */, 0xf, 0xf, true));
+    else
+        return shift_up<P>(v);
+}
+
+// One forward step of the lane's K rows: (mo, io, do_) hold column j-1 on
+// entry, (mn, in, dn) receive column j; (mu, iu) and (md, id, dd) are the row
+// above at columns j and j-1.  FP32: the rescaled states (M, Ih, Dh); FP64:
+// (M, I, D').
+template <typename T, int P, int K>
+__device__ __forceinline__ void adj_cell_step(const AdjPair<T, P, K> &pr, const T (&mo)[K], const T (&io)[K],
+                                              const T (&do_)[K], T (&mn)[K], T (&in)[K], T (&dn)[K], T mu, T iu,
+                                              T md, T id, T dd, const T *lam)
 {
 #pragma unroll
     for (int r = 0; r < K; ++r) {
-        const T x = fma(al[r], md, fma(be[r], id, dd));
-        const T mr = lam[r] * x;
-        const T ir = fma(ep[r], iu, de[r] * mu);
-        const T dr = fma(ep[r], do_[r], ze[r] * mo[r]);
+        T mr, ir, dr;
+        if constexpr (AdjPair<T, P, K>::HAT) {
+            mr = lam[r] * fma(pr.al[r], md, fma(pr.cd[r], dd, id));
+            ir = fma(pr.ke[r], iu, pr.kd[r] * mu);
+            dr = fma(pr.ep[r], do_[r], mo[r]);
+        } else {
+            mr = lam[r] * fma(pr.al[r], md, fma(pr.be[r], id, dd));
+            ir = fma(pr.ep[r], iu, pr.de[r] * mu);
+            dr = fma(pr.ep[r], do_[r], pr.ze[r] * mo[r]);
+        }
         md = mo[r];
         id = io[r];
         dd = do_[r];
@@ -251,30 +307,60 @@ __device__ __forceinline__ void adj_cell_step(const T (&mo)[K], const T (&io)[K]
     }
 }
 
+// The values a lane receives from the lane above at one step: (M, I, D) of
+// its last row, with the first lane's row-0 boundary D added in (through Ih
+// with the rescaled states, through D' otherwise).
+template <typename T, int P, int K>
+__device__ __forceinline__ void adj_from_above(const AdjPair<T, P, K> &pr, const T (&M)[K], const T (&I)[K],
+                                               const T (&D)[K], T &mu, T &iu, T &du)
+{
+    constexpr bool HAT = AdjPair<T, P, K>::HAT;
+    mu = adj_up<T, P>(M[K - 1]);
+    iu = adj_up<T, P>(I[K - 1]) + (HAT ? pr.edge : (T)0);
+    du = adj_up<T, P>(D[K - 1]) + (HAT ? (T)0 : pr.edge);
+}
+
 // Checkpointed forward of the wave's pairs.  ck: the workgroup's slice,
 // [S/CB][3K+3][64] values (lane state M, I, D and the diagonal md, id, dd
-// before steps 0, CB, 2 CB, ...).  Returns, in lane P-1 of each group, the
-// scaled row-m sum.
+// before steps 0, CB, 2 CB, ...).  Returns the scaled row-m sum, in the lane
+// that holds the absorbing row (FP32: its Dh, flushed into FP64 every 64
+// steps; nothing reads that Dh, so zeroing it is invisible to the backward)
+// or in lane P-1 of each group (FP64: the passed-down I of the last row).
 template <typename T, int K>
 struct AdjCk {
     static constexpr int V = 3 * K + 3;  // values per lane per checkpoint
 };
 
+template <typename T, int P, int K>
+__device__ __forceinline__ T adj_take_dm(const AdjPair<T, P, K> &pr, T (&D)[K])
+{
+    T dm = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        dm = r == pr.rml ? D[r] : dm;
+        D[r] = r == pr.rml ? (T)0 : D[r];
+    }
+    return dm;
+}
+
 template <typename T, int P, int K, int CB>
 __device__ __forceinline__ double adj_forward(const AdjPair<T, P, K> &pr, T *ck)
 {
+    constexpr bool HAT = AdjPair<T, P, K>::HAT;
     constexpr int V = AdjCk<T, K>::V;
     const int S = pr.S;
-    const T edge = pr.edge();
     T M[K], I[K], D[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) M[r] = I[r] = D[r] = (T)0;
-    T md = 0, id = 0, dd = edge;
+    T md = 0, id = HAT ? pr.edge : (T)0, dd = HAT ? (T)0 : pr.edge;
     double acc = 0.0;  // row-m sum: partial sums in T over 64 steps, then FP64
     T part = 0;
     for (int s0 = 0; s0 < S; s0 += CB) {
         if ((s0 & 63) == 0) {
-            acc += (double)part;
+            if constexpr (HAT)
+                acc += (double)adj_take_dm<T, P, K>(pr, D);
+            else
+                acc += (double)part;
             part = 0;
         }
         T *cq = ck + (int64_t)(s0 / CB) * V * 64 + pr.lane;
@@ -289,21 +375,23 @@ __device__ __forceinline__ double adj_forward(const AdjPair<T, P, K> &pr, T *ck)
         cq[(3 * K + 2) * 64] = dd;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
-            const T mu = shift_up<P>(M[K - 1]);
-            const T iu = shift_up<P>(I[K - 1]);
-            const T du = shift_up<P>(D[K - 1]) + edge;
+            T mu, iu, du;
+            adj_from_above<T, P, K>(pr, M, I, D, mu, iu, du);
             T lam[K];
             const char *e = pr.ecol(s0 + c);
 #pragma unroll
             for (int r = 0; r < K; ++r) lam[r] = *(const T *)(e + r * AdjCfg<T, P, K>::ROW_BYTES);
-            adj_cell_step<T, K>(M, I, D, M, I, D, mu, iu, md, id, dd, lam, pr.al, pr.be, pr.de, pr.ep, pr.ze);
+            adj_cell_step<T, P, K>(pr, M, I, D, M, I, D, mu, iu, md, id, dd, lam);
             md = mu;
             id = iu;
             dd = du;
-            part += I[K - 1];
+            if constexpr (!HAT) part += I[K - 1];
         }
     }
-    return acc + (double)part;
+    if constexpr (HAT)
+        return acc + (double)adj_take_dm<T, P, K>(pr, D);  // the last M of that row is zero
+    else
+        return acc + (double)part;
 }
 
 template <typename T, int K>
@@ -326,33 +414,51 @@ struct AdjSums {
 // Checkpoints are R blocks of CB steps apart: fine block f of a checkpoint
 // interval is rebuilt by advancing f CB steps from the checkpoint and then
 // recomputing its CB steps into registers.
+//
+// FP32 (rescaled states), with Bl = lam B_M:
+//   B_M(i,j)  = al_{i+1} Bl(i+1,j+1) + kd_{i+1} B_Ih(i+1,j) + B_Dh(i,j+1)
+//   B_Ih(i,j) =          Bl(i+1,j+1) + ke_{i+1} B_Ih(i+1,j)
+//   B_Dh(i,j) = cd_{i+1} Bl(i+1,j+1) + ep_i     B_Dh(i,j+1)
+// seeded with B_Dh = bscale on the absorbing row (L is its row sum), which
+// that row's unit coefficients carry to every column.  FP64 (M, I, D'): the
+// recurrences of the file header, seeded through B_I below the group's last
+// lane.
 template <typename T, int P, int K, int CB, int R = 1>
 __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T *ck, T bscale, AdjSums<T, K> &A)
 {
+    constexpr bool HAT = AdjPair<T, P, K>::HAT;
     using C = AdjCfg<T, P, K>;
     using V2 = typename Pair2<T>::V;
     constexpr int V = AdjCk<T, K>::V;
     const int t = pr.t, S = pr.S;
-    const T edge = pr.edge();
-    // parameters of the row below the lane's last row: the next lane's first
-    // row, or below the group a virtual row that only passes B_I up.  In
-    // 32-lane groups the group's last lane receives the next group's values
-    // from the lane shift: the parameters are replaced once per tile, and the
-    // shifted B_I and Bl are multiplied by keep = 0 there.
-    // Every lane runs the shifts (a DPP move under a lane mask reads 0 from
-    // the lanes the mask turns off), and the last lane is masked afterwards.
+    // coefficients of the row below the lane's last row: the next lane's
+    // first row; in the group's last lane the shift brings the next group's
+    // (or nothing), and keep = 0 masks it and the B values it sends.  Every
+    // lane runs the shifts (a DPP move under a lane mask reads 0 from the
+    // lanes the mask turns off).
     const bool last = t == P - 1;
     const T keep = last ? (T)0 : (T)1;
-    const T an_x = keep * shift_down_raw<P>(pr.al[0]);
-    const T bn_x = keep * shift_down_raw<P>(pr.be[0]);
-    const T dn_x = keep * shift_down_raw<P>(pr.de[0]);
-    const T en_x = fma(keep, shift_down_raw<P>(pr.ep[0]), (T)1 - keep);
-    const T edge_bi = last ? bscale : (T)0;
+    T an_x, bn_x, dn_x, en_x, cn_x, kn_x;
+    if constexpr (HAT) {
+        an_x = keep * shift_down_raw<P>(pr.al[0]);
+        cn_x = keep * shift_down_raw<P>(pr.cd[0]);
+        dn_x = keep * shift_down_raw<P>(pr.kd[0]);
+        kn_x = keep * shift_down_raw<P>(pr.ke[0]);
+        bn_x = en_x = (T)0;
+    } else {
+        an_x = keep * shift_down_raw<P>(pr.al[0]);
+        bn_x = keep * shift_down_raw<P>(pr.be[0]);
+        dn_x = keep * shift_down_raw<P>(pr.de[0]);
+        en_x = fma(keep, shift_down_raw<P>(pr.ep[0]), (T)1 - keep);
+        cn_x = kn_x = (T)0;
+    }
+    const T edge_bi = (!HAT && last) ? bscale : (T)0;
 
     T BI[K], BD[K], BL[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) {
-        BI[r] = BD[r] = BL[r] = (T)0;
+        BI[r] = BL[r] = (T)0;
+        BD[r] = (HAT && r == pr.rml) ? bscale : (T)0;
         A.a[r] = A.b[r] = A.x[r] = A.d[r] = A.ei[r] = A.ed[r] = A.z[r] = (T)0;
     }
     T bl_dn_prev = 0;
@@ -378,15 +484,14 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
             // advance from the checkpoint at step (b / R) R CB to step q CB
 #pragma unroll 1
             for (int s = (b / R) * R * CB; s < q * CB; ++s) {
-                const T mu = shift_up<P>(F[0][0][K - 1]);
-                const T iu = shift_up<P>(F[0][1][K - 1]);
-                const T du = shift_up<P>(F[0][2][K - 1]) + edge;
+                T mu, iu, du;
+                adj_from_above<T, P, K>(pr, F[0][0], F[0][1], F[0][2], mu, iu, du);
                 T lam[K];
                 const char *e = pr.ecol(s);
 #pragma unroll
                 for (int r = 0; r < K; ++r) lam[r] = *(const T *)(e + r * C::ROW_BYTES);
-                adj_cell_step<T, K>(F[0][0], F[0][1], F[0][2], F[0][0], F[0][1], F[0][2], mu, iu, bb[0][0],
-                                    bb[0][1], bb[0][2], lam, pr.al, pr.be, pr.de, pr.ep, pr.ze);
+                adj_cell_step<T, P, K>(pr, F[0][0], F[0][1], F[0][2], F[0][0], F[0][1], F[0][2], mu, iu, bb[0][0],
+                                       bb[0][1], bb[0][2], lam);
                 bb[0][0] = mu;
                 bb[0][1] = iu;
                 bb[0][2] = du;
@@ -396,16 +501,13 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
         // recompute the block as a wavefront
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
-            bb[c + 1][0] = shift_up<P>(F[c][0][K - 1]);
-            bb[c + 1][1] = shift_up<P>(F[c][1][K - 1]);
-            bb[c + 1][2] = shift_up<P>(F[c][2][K - 1]) + edge;
+            adj_from_above<T, P, K>(pr, F[c][0], F[c][1], F[c][2], bb[c + 1][0], bb[c + 1][1], bb[c + 1][2]);
             T lam[K];
             const char *e = pr.ecol(q * CB + c);
 #pragma unroll
             for (int r = 0; r < K; ++r) lam[r] = *(const T *)(e + r * C::ROW_BYTES);
-            adj_cell_step<T, K>(F[c][0], F[c][1], F[c][2], F[c + 1][0], F[c + 1][1], F[c + 1][2], bb[c + 1][0],
-                                bb[c + 1][1], bb[c][0], bb[c][1], bb[c][2], lam, pr.al, pr.be, pr.de, pr.ep,
-                                pr.ze);
+            adj_cell_step<T, P, K>(pr, F[c][0], F[c][1], F[c][2], F[c + 1][0], F[c + 1][1], F[c + 1][2],
+                                   bb[c + 1][0], bb[c + 1][1], bb[c][0], bb[c][1], bb[c][2], lam);
         }
 
         // reverse wavefront over the block
@@ -420,29 +522,42 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
                 w[r] = v.y;
             }
             const T bi_dn = fma(keep, shift_down_raw<P>(BI[0]), edge_bi);
-            const T bl_dn = keep * shift_down_raw<P>(BL[0]);  // enters B_D' of the last row directly
+            const T bl_dn = keep * shift_down_raw<P>(BL[0]);  // Bl of the row below, next column
             T bid = bi_dn;            // B_I of the row below, this column
             T bl_below = bl_dn_prev;  // Bl of the row below, next column
 #pragma unroll
             for (int r = K - 1; r >= 0; --r) {
                 const T bld = bl_below;
-                const T an = (r == K - 1) ? an_x : pr.al[r + 1];
-                const T bnr = (r == K - 1) ? bn_x : pr.be[r + 1];
-                const T dn = (r == K - 1) ? dn_x : pr.de[r + 1];
-                const T en = (r == K - 1) ? en_x : pr.ep[r + 1];
-                const T tb = bnr * bld;
-                const T bi = fma(en, bid, tb);
-                const T bd = fma(pr.ep[r], BD[r], bld);  // B_D' = Bl below-right + eps B_D' right
-                const T bm = fma(an, bld, fma(dn, bid, pr.ze[r] * BD[r]));
-                const T bl = lam[r] * bm;
                 // forward values around (i, j): row above at j and j-1, own row at j-1 and j
                 const T mu = (r == 0) ? bb[c + 1][0] : F[c + 1][0][r - 1];
                 const T iu = (r == 0) ? bb[c + 1][1] : F[c + 1][1][r - 1];
                 const T mdg = (r == 0) ? bb[c][0] : F[c][0][r - 1];
                 const T idg = (r == 0) ? bb[c][1] : F[c][1][r - 1];
                 const T ddg = (r == 0) ? bb[c][2] : F[c][2][r - 1];
+                T bi, bd, bm;
+                if constexpr (HAT) {
+                    const T an = (r == K - 1) ? an_x : pr.al[r + 1];
+                    const T cn_ = (r == K - 1) ? cn_x : pr.cd[r + 1];
+                    const T dn = (r == K - 1) ? dn_x : pr.kd[r + 1];
+                    const T kn = (r == K - 1) ? kn_x : pr.ke[r + 1];
+                    bi = fma(kn, bid, bld);
+                    bd = fma(pr.ep[r], BD[r], cn_ * bld);
+                    bm = fma(an, bld, fma(dn, bid, BD[r]));
+                } else {
+                    const T an = (r == K - 1) ? an_x : pr.al[r + 1];
+                    const T bnr = (r == K - 1) ? bn_x : pr.be[r + 1];
+                    const T dn = (r == K - 1) ? dn_x : pr.de[r + 1];
+                    const T en = (r == K - 1) ? en_x : pr.ep[r + 1];
+                    bi = fma(en, bid, bnr * bld);
+                    bd = fma(pr.ep[r], BD[r], bld);  // B_D' = Bl below-right + eps B_D' right
+                    bm = fma(an, bld, fma(dn, bid, pr.ze[r] * BD[r]));
+                }
+                const T bl = lam[r] * bm;
                 A.a[r] = fma(mdg, bl, A.a[r]);
-                A.b[r] = fma(fma(pr.be[r], idg, ddg), bl, A.b[r]);  // (beta I + D')_diag Bl
+                if constexpr (HAT)
+                    A.b[r] = fma(fma(pr.cd[r], ddg, idg), bl, A.b[r]);  // (Ih + cD Dh)_diag Bl
+                else
+                    A.b[r] = fma(fma(pr.be[r], idg, ddg), bl, A.b[r]);  // (beta I + D')_diag Bl
                 A.x[r] = fma(w[r] * F[c + 1][0][r], bm, A.x[r]);
                 A.d[r] = fma(mu, bi, A.d[r]);
                 A.ei[r] = fma(iu, bi, A.ei[r]);
@@ -460,8 +575,11 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
 }
 
 // Expected uses per row, g = coefficient x sum / (L_s 2^SB) (lam_match by
-// sum over the row's M entries), times the pair's upstream gradient u, added
-// into the per-read-base gradient array.
+// alpha + beta uses - mismatch uses), times the pair's upstream gradient u,
+// added into the per-read-base gradient array.  The coefficient is the one
+// the sum's backward value multiplies in the DP: FP32 alpha, kD (delta's),
+// kE and eps (eps's two terms), 1 (zeta's: M -> Dh has a unit coefficient);
+// FP64 alpha, delta, eps, zeta'.  beta's sum already holds beta.
 template <typename T, int P, int K>
 __device__ __forceinline__ void adj_emit(const AdjArgs &A, const AdjPair<T, P, K> &pr, double u, double inv,
                                          const AdjSums<T, K> &s)
@@ -471,14 +589,24 @@ __device__ __forceinline__ void adj_emit(const AdjArgs &A, const AdjPair<T, P, K
         const int i = pr.t * K + r;
         if (i >= pr.m) continue;
         const double ga = (double)pr.al[r] * (double)s.a[r] * inv;
-        const double gb = (double)s.b[r] * inv;  // beta already inside the sum
+        const double gb = (double)s.b[r] * inv;
         const double gx = (double)s.x[r] * inv;
+        double gd, ge, gz;
+        if constexpr (AdjPair<T, P, K>::HAT) {
+            gd = (double)pr.kd[r] * (double)s.d[r] * inv;
+            ge = ((double)pr.ke[r] * (double)s.ei[r] + (double)pr.ep[r] * (double)s.ed[r]) * inv;
+            gz = (double)s.z[r] * inv;
+        } else {
+            gd = (double)pr.de[r] * (double)s.d[r] * inv;
+            ge = (double)pr.ep[r] * ((double)s.ei[r] + (double)s.ed[r]) * inv;
+            gz = (double)pr.ze[r] * (double)s.z[r] * inv;
+        }
         float *o = A.grad_out + (pr.ro + i) * 7;
         atomicAdd(o + 0, (float)(u * ga));
         atomicAdd(o + 1, (float)(u * gb));
-        atomicAdd(o + 2, (float)(u * (double)pr.de[r] * (double)s.d[r] * inv));
-        atomicAdd(o + 3, (float)(u * (double)pr.ep[r] * ((double)s.ei[r] + (double)s.ed[r]) * inv));
-        atomicAdd(o + 4, (float)(u * (double)pr.ze[r] * (double)s.z[r] * inv));
+        atomicAdd(o + 2, (float)(u * gd));
+        atomicAdd(o + 3, (float)(u * ge));
+        atomicAdd(o + 4, (float)(u * gz));
         atomicAdd(o + 5, (float)(u * (ga + gb - gx)));
         atomicAdd(o + 6, (float)(u * gx));
     }
@@ -505,8 +633,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PH_ADJ_WAVES
         AdjPair<float, P, K> pr;
         pr.init(A, lds, rec, __builtin_amdgcn_readlane(rec.S, 0), A.hs_bytes);
         const double acc = adj_forward<float, P, K, kAdjC * kAdjR>(pr, ck);
-        const double Ls = __shfl(acc, g * P + P - 1);
-        const bool good = (Ls >= A.threshold) && (Ls <= 3.0e38);
+        // the absorbing row's lane holds the sum; a group with a beta below
+        // 2^-20 goes to the FP64 pass like a pair outside the FP32 range
+        const double Ls = __shfl(acc, g * P + min(pr.m / K, P - 1));
+        const uint64_t badm = __ballot(pr.bad);
+        const uint64_t gm = P == 64 ? ~0ull : (((1ull << P) - 1) << (g * P));
+        const bool good = (badm & gm) == 0 && (Ls >= A.threshold) && (Ls <= 3.0e38);
         const int SB = good ? AdjRange<float>::kProd - ilogb(Ls) : 0;
         AdjSums<float, K> sums;
         adj_backward<float, P, K, kAdjC, kAdjR>(pr, ck, good ? ldexpf(1.f, SB) : 0.f, sums);

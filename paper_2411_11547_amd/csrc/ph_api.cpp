@@ -342,8 +342,11 @@ ph_status build_adjoint(ph_plan *p)
         for (size_t a = i; a < end; a += G) {
             const size_t b = std::min(end, a + G);
             // the tile's first record has its longest haplotype
+            // steps: every lane reaches column n + 2 (the absorbing row of
+            // the rescaled states sums column n into column n + 2), rounded up
+            // to whole checkpoint intervals
             constexpr int CK = kAdjC * kAdjR;  // steps per checkpoint
-            const int S = ((items[a].r.n + P - 1 + CK - 1) / CK) * CK;
+            const int S = ((items[a].r.n + P + 1 + CK - 1) / CK) * CK;
             for (size_t k = a; k < b; ++k) {
                 recs[k] = items[k].r;
                 recs[k].S = S;

@@ -261,3 +261,23 @@ def test_adjoint_graph_replay_and_eager():
     torch.cuda.synchronize()
     compare(g_dev.cpu().numpy().astype(np.float64), ref, "eager")
     eager.close()
+
+
+def test_adjoint_gap_continuation_zero_rows():
+    """Gap-continuation Phred 0 (beta = 0) on rows below the first: the FP32
+    adjoint's rescaled insertion state cannot carry them, so those pairs are
+    recomputed by the FP64 pass; Phred 1..4 elsewhere (beta down to 0.21)
+    stays in FP32.  150-base reads in 32-lane groups, against the oracle."""
+    say("adjoint, gap continuation Phred 0")
+    prob = wl.config1(regions=2)
+    rng = np.random.default_rng(12)
+    prob.gcp_qual[:] = rng.integers(1, 5, size=len(prob.gcp_qual))
+    for r in range(0, prob.num_reads, 3):  # every third read gets a beta = 0 row
+        a, b = prob.read_offset[r], prob.read_offset[r + 1]
+        prob.gcp_qual[a + 1 + int(rng.integers(0, b - a - 1))] = 0
+    # positive upstream weights: the per-base sums of expected uses do not
+    # cancel, so the elementwise bound measures the kernel, not cancellation
+    u = rng.uniform(0.5, 1.5, size=prob.num_pairs)
+    ref, _ = oracle_grad(prob, u)
+    got, _ = gpu_grad(prob, u)
+    compare(got, ref, "gcp 0 rows")
