@@ -25,8 +25,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Forward GCUPS on 1 MI355X (binned FP32+FP64 rescue vs plain); adjoint GCUPS"
 FLOPS_PER_CELL = 11            # Eq. (1)-(3): 7 multiplications + 4 additions
-VALU_PER_CELL = 6              # FP32 instructions per cell of the rescaled-state sweep (4 FMA + 2 MUL)
-VITERBI_VALU_PER_CELL = 9      # the max-product cell: 6 MUL + 3 MAX
+VALU_PER_CELL = 5              # FP32 instructions per cell of the rescaled-state sweep (4 FMA + 1 MUL)
+VITERBI_VALU_PER_CELL = 8      # the max-product cell: 5 MUL + 3 MAX
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector peak
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes/clk x clock
 

@@ -54,9 +54,11 @@ typedef enum {
 enum {
     PH_PAIR_FP32 = 0,           /* FP32 sweep, scaled sum above the underflow threshold */
     PH_PAIR_FP64 = 1,           /* recomputed by the FP64 sweep: the FP32 sum was out of range,
-                                   or a read row below the first has beta < 2^-20 (the FP32
-                                   sweep's rescaled states divide by beta; Phred gap
-                                   continuation 0 gives beta = 0) */
+                                   or a read row i below the first has alpha_i < 2^-20 or
+                                   eps_i delta_{i-1} / delta_i > 2^20 (the FP32 sweep's
+                                   rescaled states divide by both; Phred gap-open qualities
+                                   of 3 or less, a gap-open quality rising by more than 60
+                                   between neighbouring bases, or explicit delta = 0) */
     PH_PAIR_FP64_FLOOR = 2,     /* FP64 sweep, but below its own range floor: unreliable */
     PH_PAIR_FP32_UNRESCUED = 3  /* FP32 below threshold in a mode without rescue */
 };
@@ -161,11 +163,12 @@ ph_status ph_viterbi_batch(ph_plan *plan, const ph_problem *problem,
  * every read base, u = grad_log10L[P] (device, double).  The derivative of
  * Eq. (1)-(4) run backwards; d log10 L / d log10 theta is the posterior
  * expected number of uses of theta.  The call runs its own checkpointed FP32
- * forward (every lane's state, i.e. every K-th row, every 4 columns) and
+ * forward (every lane's state, i.e. every K-th row, every 8 columns) and
  * then the reverse sweep, so it needs no preceding forward call.  Pairs
  * whose scaled FP32 sum falls below the plan's rescue threshold (or
- * overflows), or with a read row below the first whose beta is below 2^-20,
- * are redone in FP64, as in the forward; only pairs below the
+ * overflows), or with a read row below the first whose beta is below 2^-20
+ * (the adjoint's rescaled states divide by beta; Phred gap continuation 0
+ * gives beta = 0), are redone in FP64; only pairs below the
  * FP64 floor (log10 L < about -608) get NaN gradients, and pairs with
  * u_p = 0 contribute nothing.  The gradient buffer is overwritten.  Reads
  * longer than 319 bases give PH_ERR_UNSUPPORTED.  Sums over pairs sharing a

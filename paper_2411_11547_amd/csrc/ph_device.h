@@ -14,8 +14,8 @@ namespace ph {
 // lane shifts inside groups of P lanes: lane t receives lane t-1's value,
 // the first lane of each group receives 0.  Groups of 4 and 8 lanes shift
 // inside 16-lane rows like groups of 16: their first lanes other than lanes
-// 0, 16, 32, 48 receive the previous group's last lane, whose callers make
-// that value drop out exactly (see the forward sweep's first-row terms).
+// 0, 16, 32, 48 receive the previous group's last lane; callers clear that
+// value or give it a zero coefficient (see the forward sweep's first row).
 // ---------------------------------------------------------------------------
 template <int P>
 __device__ __forceinline__ uint32_t shift_up_zero(uint32_t v)

@@ -11,22 +11,25 @@
 // code from a per-group ring buffer in LDS.  Emissions come from a
 // per-lane table E[code][row] in LDS (Section III-B's E array).
 //
-// The FP32 sweeps carry rescaled states, Ih(i,j) = beta_{i+1} I(i,j) and
-// Dh(i,j) = D(i,j) / zeta_i, so that a sum-product cell costs one LDS value
-// and six VALU operations (the max-product cell, every sum a maximum, nine):
+// The FP32 sweeps carry rescaled states, It(i,j) = I(i,j) / delta_i and
+// Dh(i,j) = D(i,j) / zeta_i, with alpha_i folded into the row's emission
+// table (lam_ij = alpha_i * lambda_ij), so that a sum-product cell costs one
+// LDS value and five VALU operations (the max-product cell, every sum a
+// maximum, eight):
 //
-//   X  = cD_i Dh(i-1,j-1) + Ih(i-1,j-1) ;  X = alpha_i M(i-1,j-1) + X
+//   X  = M(i-1,j-1) + cD_i Dh(i-1,j-1) ;  X = cI_i It(i-1,j-1) + X
 //   M(i,j)  = lam_ij X
-//   Ih(i,j) = kD_i M(i-1,j) + kE_i Ih(i-1,j)
+//   It(i,j) = M(i-1,j) + kE_i It(i-1,j)
 //   Dh(i,j) = M(i,j-1) + eps_i Dh(i,j-1)
 //
-// with cD_i = beta_i zeta_{i-1}, kD_i = beta_{i+1} delta_i and
-// kE_i = beta_{i+1} eps_i / beta_i (beta_{m+1} read as 1, so that the last
-// read row carries I itself).  Every D term of Eq. (3) is zeta_i times a
-// column sum, so Dh stays within the range of M; Ih is at most I.  A row with
-// beta_i < 2^-20 (Phred gap continuation 0, or explicit parameters near it)
-// sends its pair to the FP64 sweep, which keeps the plain states with D
-// pre-multiplied by the next row's beta:
+// with cI_i = beta_i delta_{i-1} / alpha_i, cD_i = beta_i zeta_{i-1} /
+// alpha_i and kE_i = eps_i delta_{i-1} / delta_i.  It and Dh are column and
+// row sums of M with decaying weights, so they stay within the range of M
+// unless delta falls steeply from one row to the next.  A read row with
+// alpha_i < 2^-20 or kE_i > 2^20 (Phred gap-open qualities of 3 or less, or a
+// gap-open quality rising by more than 60 from one base to the next, or
+// explicit parameters like them) sends its pair to the FP64 sweep, which
+// keeps the plain states with D pre-multiplied by the next row's beta:
 //
 //   X  = beta_i I(i-1,j-1) + Dt(i-1,j-1) ;  X = alpha_i M(i-1,j-1) + X
 //   M(i,j) = lam_ij X
@@ -38,11 +41,12 @@
 //    lam = 0, delta = eps = 1, so I(m+1,j) = M(m,j) + I(m,j), and later rows
 //    pass I down unchanged (delta = 0, eps = 1); the last register of the
 //    group's last lane holds the quantity Section II-A sums into L, whatever
-//    m is.  Rescaled states: row m+1 has lam = alpha = 1, so
-//    M(m+1,j) = M(m,j-1) + I(m,j-1), and its Dh (eps = 1) sums that along
+//    m is.  Rescaled states: row m+1 has lam = 1, cD = 0 and cI = delta_m,
+//    so M(m+1,j) = M(m,j-1) + I(m,j-1), and its Dh (eps = 1) sums that along
 //    the row (max-product: keeps its running maximum): the row-(m+1) lane
-//    flushes it into an FP64 accumulator every 64 steps, and later rows stay
-//    exactly zero.  (The paper pads reads with
+//    flushes it into an FP64 accumulator every 64 steps.  Later rows have
+//    every coefficient 0: their M and Dh are exactly zero, and so is It from
+//    row m+3 on.  (The paper pads reads with
 //    N, which would change L if read at row pK.)
 //  * Columns past the haplotype end carry a PAD code whose emission is 0, so
 //    groups of one wave may have different n and still add only exact zeros.
@@ -215,24 +219,36 @@ __device__ __forceinline__ void cell_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md
         acc += I[K - 1];
 }
 
-// The same step with the rescaled states (M, Ih, Dh) of the FP32
-// sum-product sweep; ep holds eps, cd, kd and ke the coefficients cD, kD
-// and kE of the file header.  (eM, eI, eD) are added to the values received
+// The same step with the rescaled states (M, It, Dh) of the FP32 sweeps;
+// lam holds alpha_i lambda_ij, ci, cd, ke and ep the coefficients cI, cD, kE
+// and eps of the file header.  (eM, eI, eD) are added to the values received
 // from the lane above: the first lane's row-0 boundary (eI = beta_1 / n,
-// scaled, enters through Ih since cD = 0 on the read's first row) or, in
+// scaled, enters through It with cI = 1 on the read's first row) or, in
 // windowed mode, the stored boundary row; zero in the other lanes.
+//
+// Groups of 4 and 8 lanes: the first lane of a group other than lanes 0, 16,
+// 32, 48 receives the previous group's last row, which may be that pair's
+// absorbing row or the row below it.  keep is 0 in the first lane of every
+// group and all ones elsewhere; it clears the received M and It there.  The
+// received Dh needs no mask: it meets cD = 0 on the read's first row.
 //
 // Viterbi mode (V): every sum a maximum, as in cell_step; the rescaling by
 // positive per-row factors commutes with the maximum.
 template <typename T, int P, int K, bool W = false, bool V = false>
 __device__ __forceinline__ void cell_step_hat(T (&M)[K], T (&I)[K], T (&D)[K], T &Md, T &Id, T &Dd,
-                                              const T *lam, const T (&al)[K], const T (&cd)[K],
-                                              const T (&kd)[K], const T (&ke)[K], const T (&ep)[K], T eI,
+                                              const T *lam, const T (&ci)[K], const T (&cd)[K],
+                                              const T (&ke)[K], const T (&ep)[K], T eI, uint32_t keep,
                                               T eM = 0, T eD = 0)
 {
+    static_assert(sizeof(T) == 4, "rescaled states are an FP32 form");
     T Mu = shift_up<P>(M[K - 1]);
-    const T Iu = shift_up<P>(I[K - 1]) + eI;
+    T Iu = shift_up<P>(I[K - 1]);
     T Du = shift_up<P>(D[K - 1]);
+    if constexpr (P < 16) {
+        Mu = __builtin_bit_cast(T, __builtin_bit_cast(uint32_t, Mu) & keep);
+        Iu = __builtin_bit_cast(T, __builtin_bit_cast(uint32_t, Iu) & keep);
+    }
+    Iu += eI;
     if constexpr (W) {
         Mu += eM;
         Du += eD;
@@ -243,14 +259,14 @@ __device__ __forceinline__ void cell_step_hat(T (&M)[K], T (&I)[K], T (&D)[K], T
         const T mo = M[r], io = I[r], dol = D[r];
         T mn, in, dn;
         if constexpr (V) {
-            mn = lam[r] * fmax(fmax(al[r] * mdg, idg), cd[r] * ddg);
-            in = fmax(kd[r] * mup, ke[r] * iup);
+            mn = lam[r] * fmax(fmax(mdg, ci[r] * idg), cd[r] * ddg);
+            in = fmax(mup, ke[r] * iup);
             dn = fmax(mo, ep[r] * dol);
         } else {
-            T x = fma(cd[r], ddg, idg);
-            x = fma(al[r], mdg, x);
+            T x = fma(cd[r], ddg, mdg);
+            x = fma(ci[r], idg, x);
             mn = lam[r] * x;
-            in = fma(ke[r], iup, kd[r] * mup);
+            in = fma(ke[r], iup, mup);
             dn = fma(ep[r], dol, mo);
         }
         M[r] = mn;
@@ -290,16 +306,16 @@ __device__ __forceinline__ void window_step(T (&M)[K], T (&I)[K], T (&D)[K], T &
 }
 
 // window_step with the rescaled states: the staged boundary row holds
-// (M, Ih, Dh) and the row-0 boundary enters through Ih.
+// (M, It, Dh) and the row-0 boundary enters through It.
 template <typename T, int K, bool V>
 __device__ __forceinline__ void window_step_hat(T (&M)[K], T (&I)[K], T (&D)[K], T &Md, T &Id, T &Dd,
-                                                const T *lam, const T (&al)[K], const T (&cd)[K],
-                                                const T (&kd)[K], const T (&ke)[K], const T (&ep)[K], T edge,
-                                                const T *top, int u, int t, bool fin, T *bnd, int s, int n)
+                                                const T *lam, const T (&ci)[K], const T (&cd)[K],
+                                                const T (&ke)[K], const T (&ep)[K], T edge, const T *top, int u,
+                                                int t, bool fin, T *bnd, int s, int n)
 {
     const T tM = top[u], tI = top[64 + u], tD = top[128 + u];
     const bool first = t == 0;
-    cell_step_hat<T, 64, K, true, V>(M, I, D, Md, Id, Dd, lam, al, cd, kd, ke, ep, first ? tI + edge : (T)0,
+    cell_step_hat<T, 64, K, true, V>(M, I, D, Md, Id, Dd, lam, ci, cd, ke, ep, first ? tI + edge : (T)0, ~0u,
                                      first ? tM : (T)0, first ? tD : (T)0);
     const int j = s - 62;  // the last lane's column
     if (!fin && t == 63 && j >= 1 && j <= n) {
@@ -310,12 +326,53 @@ __device__ __forceinline__ void window_step_hat(T (&M)[K], T (&I)[K], T (&D)[K],
     }
 }
 
-// beta of read position pos below 2^-20: the rescaled states cannot carry
-// that row (kE divides by beta)
-__device__ __forceinline__ bool beta_tiny(const DevProblem &pb, const double *lin, int64_t pos)
+// Coefficients of the rescaled states for read row i >= 1 (0-based) from
+// its delta, zeta, eps, beta and the row above's delta and zeta: the factor
+// alpha_i that goes into the row's emissions, cI, cD and kE.  Returns false
+// when the row is outside what the FP32 states carry (alpha_i < 2^-20 or
+// kE > 2^20); the coefficients are then 0 and the pair goes to the FP64
+// sweep.  FP32 form for Phred qualities (alpha = 1 - delta - zeta rounded in
+// FP32), FP64 form for explicit parameters; the sweep's prologue and the
+// windowed sweep's check of earlier windows call the same functions.
+__device__ __forceinline__ bool hat_coef(float dp, float zp, float d, float z, float e, float b, float &fac,
+                                         float &ci, float &cd, float &ke)
 {
-    if (lin) return !(lin[pos * 8 + 1] >= 0x1p-20);
-    return !(c_1mpf[pb.gq[pos]] >= 0x1p-20f);
+    const float a = 1.0f - d - z;
+    const float ra = __builtin_amdgcn_rcpf(a);
+    const float k = e * dp * __builtin_amdgcn_rcpf(d);
+    const bool ok = a >= 0x1p-20f && k <= 0x1p20f;
+    fac = a;
+    ci = ok ? b * dp * ra : 0.0f;
+    cd = ok ? b * zp * ra : 0.0f;
+    ke = ok ? k : 0.0f;
+    return ok;
+}
+
+__device__ __forceinline__ bool hat_coef(const RowPar &p, const RowPar &pp, double &fac, double &ci, double &cd,
+                                         double &ke)
+{
+    const double k = p.e * pp.d / p.d;
+    const bool ok = p.a >= 0x1p-20 && k <= 0x1p20;
+    fac = p.a;
+    ci = ok ? p.b * pp.d / p.a : 0.0;
+    cd = ok ? p.b * pp.z / p.a : 0.0;
+    ke = ok ? k : 0.0;
+    return ok;
+}
+
+// read row i >= 1 (0-based) at read offset ro cannot be carried by the FP32
+// rescaled states (see hat_coef)
+__device__ __forceinline__ bool hat_row_unsafe(const DevProblem &pb, const double *lin, int64_t ro, int i)
+{
+    if (lin) {
+        double fac, ci, cd, ke;
+        return !hat_coef(load_row(pb, lin, ro + i, c_prob), load_row(pb, lin, ro + i - 1, c_prob), fac, ci, cd,
+                         ke);
+    }
+    float fac, ci, cd, ke;
+    const int64_t pos = ro + i;
+    return !hat_coef(c_pf[pb.iq[pos - 1]], c_pf[pb.dq[pos - 1]], c_pf[pb.iq[pos]], c_pf[pb.dq[pos]],
+                     c_pf[pb.gq[pos]], c_1mpf[pb.gq[pos]], fac, ci, cd, ke);
 }
 
 // Sweep one tile: up to G = 64/P pairs, one per lane group.  Group g takes
@@ -370,10 +427,11 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     // ---- prologue: parameters of my rows, my slice of the E table ----------
     // Loads use clamped row indices so that they stay inside the read;
     // padding rows then get their absorbing parameters by select.  With the
-    // rescaled states the absorbing row m (0-based) has lam = 1 for every
-    // code and alpha = eps = 1, the rows past it are all zero, and the read's
-    // first row has alpha = cD = kD = kE = 0 (the row above it is the DP
-    // boundary: M = I = 0, its D enters as the Ih edge value).
+    // rescaled states the read's first row has cI = 1 and cD = kE = 0 (the
+    // row above it is the DP boundary: M = I = 0, its D enters as the It edge
+    // value), the absorbing row m (0-based) has lam = 1 for every code,
+    // cI = delta_{m-1}, cD = kE = 0 and eps = 1, and the rows past it have
+    // every coefficient 0.
     char *E = lds;
     char *mine = E + lane * 8;
     uint16_t *ring = (uint16_t *)(lds + C::E_BYTES + g * C::RING_BYTES);
@@ -383,83 +441,86 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     const int mload = m > 0 ? m : 1;
     const int base = r0 + t * K;  // my first row (0-based)
     T al[K], be[K], de[K], ep[K], zt[K];  // plain states
-    T cd[K], kd[K], ke[K];                // rescaled states (with al and ep)
+    T ci[K], cd[K], ke[K];                // rescaled states (with ep)
     T edge = 0;
-    bool bad = false;  // rescaled states: one of my rows has beta below 2^-20
+    bool bad = false;  // rescaled states: one of my rows is outside what they carry
     if (sizeof(T) == 4 && !lin) {
         // FP32 sweep, Phred mode: all of the lane's loads issued at once,
         // decoded through the FP32 tables (1 - p and p/3 rounded from FP64);
-        // the E table first, then the transition parameters
-        {
-            uint32_t bq[C::KP], code[C::KP];
+        // the transition parameters first, then the E table with each real
+        // row's alpha folded in
+        uint32_t bq[C::KP], code[C::KP], iq[K + 1], dq[K + 1], gq[K];
 #pragma unroll
-            for (int r = 0; r < C::KP; ++r) {
-                const int64_t pos = ro + min(base + r, mload - 1);
-                bq[r] = pb.bq[pos];
-                code[r] = clamp_code(pb.read_bases[pos]);
+        for (int r = 0; r < C::KP; ++r) {
+            const int64_t pos = ro + min(base + r, mload - 1);
+            bq[r] = pb.bq[pos];
+            code[r] = clamp_code(pb.read_bases[pos]);
+        }
+        // iq[r], dq[r]: row base + r - 1 (the row above row r); gq[r]: row base + r
+#pragma unroll
+        for (int r = 0; r <= K; ++r) {
+            const int64_t pa = ro + min(max(base + r - 1, 0), mload - 1);
+            iq[r] = pb.iq[pa];
+            dq[r] = pb.dq[pa];
+            if (r < K) gq[r] = pb.gq[ro + min(base + r, mload - 1)];
+        }
+        float fac[C::KP];
+#pragma unroll
+        for (int r = 0; r < C::KP; ++r) fac[r] = 0.0f;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int i = base + r;
+            const bool real = i < m;
+            const float e = c_pf[gq[r]];
+            if constexpr (HAT) {
+                float f, c1, c2, k;
+                const bool ok = hat_coef(c_pf[iq[r]], c_pf[dq[r]], c_pf[iq[r + 1]], c_pf[dq[r + 1]], e,
+                                         c_1mpf[gq[r]], f, c1, c2, k);
+                const bool inner = real && i >= 1;
+                bad = bad || (inner && !ok);
+                fac[r] = inner ? f : 1.0f;
+                ci[r] = inner ? (T)c1 : i == 0 ? (T)1 : i == m ? (T)c_pf[iq[r]] : (T)0;
+                cd[r] = inner ? (T)c2 : (T)0;
+                ke[r] = inner ? (T)k : (T)0;
+                ep[r] = real ? (T)e : (i == m ? (T)1 : (T)0);
+            } else {
+                const float d = c_pf[iq[r + 1]], z = c_pf[dq[r + 1]];
+                fac[r] = 1.0f;
+                al[r] = real ? (T)(1.0f - d - z) : (T)0;
+                be[r] = real ? (T)c_1mpf[gq[r]] : (T)0;
+                de[r] = real ? (T)d : (i == m ? (T)1 : (T)0);
+                ep[r] = real ? (T)e : (T)1;
+                const float bn = c_1mpf[pb.gq[ro + min(i + 1, mload - 1)]];
+                zt[r] = (real && i + 1 < m) ? (T)(bn * z) : (T)0;
+            }
+        }
+        if (t == 0 && m > 0 && r0 == 0) edge = ldexpf(c_1mpf[gq[0]], Range<T>::kExp) / (float)n;
+#pragma unroll
+        for (int q = 0; q < C::NPL; ++q) {
+            float lm[C::RPP], lx[C::RPP];
+            bool one[C::RPP];
+#pragma unroll
+            for (int rr = 0; rr < C::RPP; ++rr) {
+                const int r = q * C::RPP + rr;
+                const bool real = (r < K) && (base + r < m);
+                one[rr] = HAT && (r < K) && (base + r == m);
+                lm[rr] = real ? c_1mpf[bq[r]] * fac[r] : 0.f;
+                lx[rr] = real ? c_pd3f[bq[r]] * fac[r] : 0.f;
             }
 #pragma unroll
-            for (int q = 0; q < C::NPL; ++q) {
-                float lm[C::RPP], lx[C::RPP];
-                bool one[C::RPP];
+            for (int c = 0; c < kCodes; ++c) {
+                T v[C::RPP];
 #pragma unroll
                 for (int rr = 0; rr < C::RPP; ++rr) {
                     const int r = q * C::RPP + rr;
-                    const bool real = (r < K) && (base + r < m);
-                    one[rr] = HAT && (r < K) && (base + r == m);
-                    lm[rr] = real ? c_1mpf[bq[r]] : 0.f;
-                    lx[rr] = real ? c_pd3f[bq[r]] : 0.f;
+                    const bool match = code[r] == (uint32_t)c || code[r] == 4u || c == 4;
+                    v[rr] = one[rr] ? (T)1 : c == kPad ? (T)0 : (T)(match ? lm[rr] : lx[rr]);
                 }
-#pragma unroll
-                for (int c = 0; c < kCodes; ++c) {
-                    T v[C::RPP];
-#pragma unroll
-                    for (int rr = 0; rr < C::RPP; ++rr) {
-                        const int r = q * C::RPP + rr;
-                        const bool match = code[r] == (uint32_t)c || code[r] == 4u || c == 4;
-                        v[rr] = one[rr] ? (T)1 : c == kPad ? (T)0 : (T)(match ? lm[rr] : lx[rr]);
-                    }
-                    if constexpr (sizeof(T) == 4)
-                        *(float2 *)(mine + c * C::CODE_BYTES + q * 512) = make_float2(v[0], v[1]);
-                    else
-                        *(double *)(mine + c * C::CODE_BYTES + q * 512) = v[0];
-                }
+                if constexpr (sizeof(T) == 4)
+                    *(float2 *)(mine + c * C::CODE_BYTES + q * 512) = make_float2(v[0], v[1]);
+                else
+                    *(double *)(mine + c * C::CODE_BYTES + q * 512) = v[0];
             }
-        }
-        {
-            // dq[r]: row base + r - 1 (the row above row r); gq[r]: row base + r
-            uint32_t iq[K], dq[K + 1], gq[K + 1];
-#pragma unroll
-            for (int r = 0; r <= K; ++r) {
-                gq[r] = pb.gq[ro + min(base + r, mload - 1)];
-                dq[r] = pb.dq[ro + min(max(base + r - 1, 0), mload - 1)];
-                if (r < K) iq[r] = pb.iq[ro + min(base + r, mload - 1)];
-            }
-#pragma unroll
-            for (int r = 0; r < K; ++r) {
-                const int i = base + r;
-                const bool real = i < m;
-                const float d = c_pf[iq[r]], z = c_pf[dq[r + 1]];
-                if constexpr (HAT) {
-                    const bool inner = real && i >= 1;
-                    const float b = c_1mpf[gq[r]], e = c_pf[gq[r]];
-                    const float bn = i + 1 < m ? c_1mpf[gq[r + 1]] : 1.0f;
-                    const bool ok = b >= 0x1p-20f;
-                    bad = bad || (inner && !ok);
-                    al[r] = i == 0 ? (T)0 : real ? (T)(1.0f - d - z) : (i == m ? (T)1 : (T)0);
-                    cd[r] = inner ? (T)(b * c_pf[dq[r]]) : (T)0;
-                    kd[r] = inner ? (T)(bn * d) : (T)0;
-                    ke[r] = (inner && ok) ? (T)(bn * e * __builtin_amdgcn_rcpf(b)) : (T)0;
-                    ep[r] = real ? (T)e : (i == m ? (T)1 : (T)0);
-                } else {
-                    al[r] = real ? (T)(1.0f - d - z) : (T)0;
-                    be[r] = real ? (T)c_1mpf[gq[r]] : (T)0;
-                    de[r] = real ? (T)d : (i == m ? (T)1 : (T)0);
-                    ep[r] = real ? (T)c_pf[gq[r]] : (T)1;
-                    zt[r] = (real && i + 1 < m) ? (T)(c_1mpf[gq[r + 1]] * z) : (T)0;
-                }
-            }
-            if (t == 0 && m > 0 && r0 == 0) edge = ldexpf(c_1mpf[gq[0]], Range<T>::kExp) / (float)n;
         }
     } else {
         // FP64 sweep or explicit parameters: one row at a time in FP64, the
@@ -472,15 +533,14 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             const bool real = i < m;
             if constexpr (HAT) {
                 const bool inner = real && i >= 1;
-                const double bn = i + 1 < m ? load_beta(pb, lin, ro + i + 1, c_prob) : 1.0;
-                const double zp = inner ? load_row(pb, lin, ro + i - 1, c_prob).z : 0.0;
-                const bool ok = p.b >= 0x1p-20;
+                const RowPar pp = load_row(pb, lin, ro + min(max(i - 1, 0), mload - 1), c_prob);
+                double f, c1, c2, k;
+                const bool ok = hat_coef(p, pp, f, c1, c2, k);
                 bad = bad || (inner && !ok);
-                *slot(0, r) = i == 0 ? (T)0 : real ? (T)p.a : (i == m ? (T)1 : (T)0);
-                *slot(1, r) = inner ? (T)(p.b * zp) : (T)0;
-                *slot(2, r) = inner ? (T)(bn * p.d) : (T)0;
-                *slot(3, r) = (inner && ok) ? (T)(bn * p.e / p.b) : (T)0;
-                *slot(4, r) = real ? (T)p.e : (i == m ? (T)1 : (T)0);
+                *slot(0, r) = inner ? (T)c1 : i == 0 ? (T)1 : i == m ? (T)pp.d : (T)0;
+                *slot(1, r) = inner ? (T)c2 : (T)0;
+                *slot(2, r) = inner ? (T)k : (T)0;
+                *slot(3, r) = real ? (T)p.e : (i == m ? (T)1 : (T)0);
             } else {
                 const double bn = load_beta(pb, lin, ro + min(i + 1, mload - 1), c_prob);
                 *slot(0, r) = real ? (T)p.a : (T)0;
@@ -493,11 +553,10 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
 #pragma unroll
         for (int r = 0; r < K; ++r) {
             if constexpr (HAT) {
-                al[r] = *slot(0, r);
+                ci[r] = *slot(0, r);
                 cd[r] = *slot(1, r);
-                kd[r] = *slot(2, r);
-                ke[r] = *slot(3, r);
-                ep[r] = *slot(4, r);
+                ke[r] = *slot(2, r);
+                ep[r] = *slot(3, r);
             } else {
                 al[r] = *slot(0, r);
                 be[r] = *slot(1, r);
@@ -507,7 +566,8 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             }
         }
         if (t == 0 && m > 0 && r0 == 0) edge = (T)(ldexp(load_beta(pb, lin, ro, c_prob), Range<T>::kExp) / (double)n);
-        // E[c][row] = lam of the row against haplotype code c (N matches all, PAD = 0)
+        // E[c][row] = lam of the row against haplotype code c (N matches all,
+        // PAD = 0); rescaled states: times alpha on the read's rows after the first
 #pragma unroll 1
         for (int r = 0; r < C::KP; ++r) {
             const int i = base + r;
@@ -515,8 +575,9 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             const RowPar p = load_row(pb, lin, ro + ic, c_prob);
             const bool real = (r < K) && (i < m);
             const bool one = HAT && (r < K) && (i == m);
+            const double f = (HAT && i >= 1) ? p.a : 1.0;
             const uint32_t code = clamp_code(pb.read_bases[ro + ic]);
-            const T lm = real ? (T)p.lm : (T)0, lx = real ? (T)p.lx : (T)0;
+            const T lm = real ? (T)(p.lm * f) : (T)0, lx = real ? (T)(p.lx * f) : (T)0;
 #pragma unroll
             for (int c = 0; c < kCodes; ++c) {
                 const bool match = code == (uint32_t)c || code == 4u || c == 4;
@@ -532,9 +593,8 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     // first row only through beta (with the diagonal) and eps (from above),
     // and both are set to 0 here, which is exact because row 0 has I = 0.  In
     // later windows of a long read the row above is a real stored row and
-    // keeps its terms.  (Rescaled states: the read's first row has zero
-    // coefficients on every received value but the Ih diagonal, and that one
-    // is exactly zero in the previous group's last row.)
+    // keeps its terms.  (Rescaled states: the received M and It are cleared
+    // in the first lane of each group, see cell_step_hat.)
     T epI0 = ep[0];
     if constexpr (!HAT) {
         if (t == 0 && r0 == 0) {
@@ -542,13 +602,15 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             epI0 = 0;
         }
     }
-    // rescaled states: the pair goes to the FP64 sweep if any of its rows has
-    // a beta below 2^-20 (rows of earlier windows are checked by the final one)
+    const uint32_t keep = t == 0 ? 0u : ~0u;
+    // rescaled states: the pair goes to the FP64 sweep if any of its rows is
+    // outside what they carry (rows of earlier windows are checked by the
+    // final one)
     bool gbad = false;
     if constexpr (HAT) {
         if constexpr (W) {
             if (fin)
-                for (int i = 1 + t; i < r0; i += 64) bad = bad || beta_tiny(pb, lin, ro + i);
+                for (int i = 1 + t; i < r0; i += 64) bad = bad || hat_row_unsafe(pb, lin, ro, i);
         }
         const uint64_t bm = __ballot(bad);
         const uint64_t gm = P == 64 ? ~0ull : (((1ull << P) - 1) << (g * P));
@@ -617,15 +679,15 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             for (int u = 0; u < cnt; u += 2) {
                 load_lam<T, P, K>(lb, ebase_lane + hp[u + 1]);
                 if constexpr (W) {
-                    window_step_hat<T, K, V>(M, I, D, Md, Id, Dd, la, al, cd, kd, ke, ep, edge, top, u, t, fin,
-                                             bnd, s0 + u, n);
+                    window_step_hat<T, K, V>(M, I, D, Md, Id, Dd, la, ci, cd, ke, ep, edge, top, u, t, fin, bnd,
+                                             s0 + u, n);
                     load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
-                    window_step_hat<T, K, V>(M, I, D, Md, Id, Dd, lb, al, cd, kd, ke, ep, edge, top, u + 1, t,
-                                             fin, bnd, s0 + u + 1, n);
+                    window_step_hat<T, K, V>(M, I, D, Md, Id, Dd, lb, ci, cd, ke, ep, edge, top, u + 1, t, fin,
+                                             bnd, s0 + u + 1, n);
                 } else {
-                    cell_step_hat<T, P, K, false, V>(M, I, D, Md, Id, Dd, la, al, cd, kd, ke, ep, edge);
+                    cell_step_hat<T, P, K, false, V>(M, I, D, Md, Id, Dd, la, ci, cd, ke, ep, edge, keep);
                     load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
-                    cell_step_hat<T, P, K, false, V>(M, I, D, Md, Id, Dd, lb, al, cd, kd, ke, ep, edge);
+                    cell_step_hat<T, P, K, false, V>(M, I, D, Md, Id, Dd, lb, ci, cd, ke, ep, edge, keep);
                 }
             }
             // the absorbing row's Dh (Viterbi: its running maximum) moves

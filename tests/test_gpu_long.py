@@ -78,9 +78,10 @@ def test_long_reads_explicit_params_and_replay():
     check_against_oracle(prob, a1, s1, log10_params=lg)
 
 
-def test_long_read_gap_continuation_zero_in_an_earlier_window():
-    """Gap-continuation Phred 0 (beta = 0) on a row of the first window of a
-    long read: the FP32 windowed sweep's final window must still send the
+def test_long_read_row_outside_fp32_states_in_an_earlier_window():
+    """An insertion gap-open quality rising from Phred 2 to 90 between rows
+    299 and 300 of a long read (kE > 2^20, outside the FP32 states), in its
+    first window: the FP32 windowed sweep's final window must still send the
     pair to the FP64 sweep, and no other pair changes status."""
     prob = long_problem()
     got0, st0 = gpu_forward(prob)
@@ -89,9 +90,11 @@ def test_long_read_gap_continuation_zero_in_an_earlier_window():
     cand = [r for r in range(prob.num_reads) if m_all[r] > 1024 and np.any(st0[r_idx == r] == binding.PAIR_FP32)]
     assert cand, "no long read with a pair finished in FP32"
     r = cand[0]
-    prob.gcp_qual[prob.read_offset[r] + 300] = 0
+    prob.ins_qual[prob.read_offset[r] + 299] = 2
+    prob.ins_qual[prob.read_offset[r] + 300] = 90
     mine = r_idx == r
-    say(f"long read {r} (m = {m_all[r]}): Phred 0 on row 300, {int((st0[mine] == 0).sum())} FP32 pairs before")
+    say(f"long read {r} (m = {m_all[r]}): gap-open Phred 2 -> 90 at row 300, "
+        f"{int((st0[mine] == 0).sum())} FP32 pairs before")
     got, st = gpu_forward(prob)
     check_against_oracle(prob, got, st)
     assert np.all(st[mine] != binding.PAIR_FP32)

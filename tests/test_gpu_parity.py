@@ -196,12 +196,11 @@ def test_ragged_lengths_every_bin():
 
 
 def test_gap_continuation_zero_rows():
-    """Gap-continuation Phred 0 (eps = 1, beta = 0) on a row below the
-    first: the FP32 sweep's rescaled insertion state (beta of the next row
-    times I) cannot carry that row, so exactly those pairs are recomputed by
-    the FP64 sweep; Phred 1..4 (beta down to 0.21) stays in FP32.  Rows at
-    both ends of the read and inside, in the default groups and in 64-lane
-    groups."""
+    """Gap-continuation Phred 0 (eps = 1, beta = 0) on rows below the first,
+    and Phred 1..4 on every row of some reads: the FP32 sweep's states divide
+    by no beta, so every such pair in the FP32 range finishes in FP32 and
+    matches the oracle.  Rows at both ends of the read and inside, in the
+    default groups and in 64-lane groups."""
     say("gap continuation Phred 0")
     prob = _ragged(41, [[20, 60, 150, 300, 63], [100, 700, 255, 31]], [[80, 200], [150, 900, 60]])
     rng = np.random.default_rng(42)
@@ -218,14 +217,59 @@ def test_gap_continuation_zero_rows():
     r_idx, _ = prob.pair_index()
     zero = np.isin(r_idx, list(zero_rows))
     inside = ref > -60.0  # well inside the FP32 range (rescue below about -64.1)
-    say(f"  {int((zero & inside).sum())} flagged and {int((~zero & inside).sum())} plain pairs in range")
-    assert (zero & inside).sum() >= 6 and (~zero & inside).sum() >= 6
+    say(f"  {int((zero & inside).sum())} pairs with Phred-0 rows in range")
+    assert (zero & inside).sum() >= 6
     for kw in (dict(), dict(force_p=64, use_graph=False)):
         got, st = gpu_forward(prob, **kw)
         check_against_oracle(prob, got, st, ref=ref)
-        assert np.all(st[zero] != binding.PAIR_FP32), st[zero]
-        assert np.all(st[zero & inside] == binding.PAIR_FP64), st[zero & inside]
-        assert np.all(st[~zero & inside] == binding.PAIR_FP32), st[~zero & inside]
+        assert np.all(st[inside] == binding.PAIR_FP32), st[inside]
+
+
+def test_rows_outside_fp32_states():
+    """Rows the FP32 sweep's rescaled states cannot carry send exactly their
+    pairs to the FP64 sweep: alpha below 2^-20 (insertion and deletion
+    gap-open Phred 3 on one row: alpha = 1 - 2 * 10^-0.3 < 0), and an
+    insertion gap-open quality rising from 2 to 90 between two rows (kE =
+    eps * delta_{i-1} / delta_i = 0.1 * 10^8.8 > 2^20).  A rise from 2 to 60
+    (kE = 10^4.8) stays in FP32.  Rows at both ends of the read and inside,
+    in the default groups and in 64-lane groups."""
+    say("rows outside the FP32 states")
+    prob = _ragged(43, [[20, 60, 150, 120, 63], [100, 90, 255, 31]], [[80, 200], [150, 300, 260]])
+    prob.gcp_qual[:] = 10
+    m_all = prob.read_lengths
+    # read -> rows with ins = del = Phred 3; on the last row, so that L stays
+    # positive (a negative alpha on an inner row can make it negative)
+    low_alpha = {0: [0], 3: [119], 6: [89]}
+    steep = {1: [1], 5: [99], 8: [30]}  # read -> rows i with ins Phred 2 at i-1 and 90 at i
+    mild = {2: [100], 7: [254]}         # the same with 60 at i: stays in FP32
+    for r, rows in low_alpha.items():
+        for i in rows:
+            assert 0 <= i < m_all[r]
+            prob.ins_qual[prob.read_offset[r] + i] = 3
+            prob.del_qual[prob.read_offset[r] + i] = 3
+    for table, hi in ((steep, 90), (mild, 60)):
+        for r, rows in table.items():
+            for i in rows:
+                assert 1 <= i < m_all[r]
+                prob.ins_qual[prob.read_offset[r] + i - 1] = 2
+                prob.ins_qual[prob.read_offset[r] + i] = hi
+    ref = oracle.forward(prob)
+    assert np.all(np.isfinite(ref))
+    r_idx, _ = prob.pair_index()
+    # alpha on the read's first row is not divided by (its M term has no alpha)
+    flagged = np.isin(r_idx, [3, 6] + list(steep))
+    inside = ref > -60.0
+    say(f"  {int((flagged & inside).sum())} flagged and {int((~flagged & inside).sum())} other pairs in range")
+    assert (flagged & inside).sum() >= 8 and (~flagged & inside).sum() >= 6
+    assert (np.isin(r_idx, [3, 6]) & inside).sum() >= 3
+    assert (np.isin(r_idx, list(mild)) & inside).sum() >= 2
+    assert (np.isin(r_idx, [0]) & inside).sum() >= 1
+    for kw in (dict(), dict(force_p=64, use_graph=False)):
+        got, st = gpu_forward(prob, **kw)
+        check_against_oracle(prob, got, st, ref=ref)
+        assert np.all(st[flagged] != binding.PAIR_FP32), st[flagged]
+        assert np.all(st[flagged & inside] == binding.PAIR_FP64), st[flagged & inside]
+        assert np.all(st[~flagged & inside] == binding.PAIR_FP32), st[~flagged & inside]
 
 
 def test_fp64_floor_status():
@@ -242,10 +286,17 @@ def test_fp64_floor_status():
     assert (st == binding.PAIR_FP64_FLOOR).any()
 
 
-def test_ungapped_closed_form_150x300():
+@pytest.mark.parametrize("gap", [0.0, 1e-30])
+def test_ungapped_closed_form_150x300(gap):
     """Explicit parameters with delta = zeta = 0 and alpha = 1: the result is
-    the ungapped scan (beta_1/n) sum over offsets of the emission product."""
-    say("ungapped closed form")
+    the ungapped scan (beta_1/n) sum over offsets of the emission product.
+    delta = 0 is outside the FP32 sweep's states (its I is scaled by
+    1/delta), so those pairs finish in FP64.  With delta = zeta = 1e-30 a
+    read against the haplotype it was copied into (log10 L near -2) changes
+    by about 1e-28 from the closed form and finishes in FP32; against the
+    other haplotypes gapped paths dominate, and those pairs are compared with
+    the oracle instead."""
+    say(f"ungapped closed form, delta = zeta = {gap}")
     rng = np.random.default_rng(7)
     m, n = 150, 300
     reads, haps = [], []
@@ -258,8 +309,8 @@ def test_ungapped_closed_form_150x300():
         haps.append("".join(h))
     prob = wl.from_strings([(reads, haps)])
     Q = 10 ** -rng.uniform(1.5, 4, len(prob.read_bases))
-    lin = np.stack([np.ones_like(Q), np.full_like(Q, 0.9), np.zeros_like(Q), np.full_like(Q, 0.1),
-                    np.zeros_like(Q), 1 - Q, Q / 3], 1)
+    lin = np.stack([np.ones_like(Q), np.full_like(Q, 0.9), np.full_like(Q, gap), np.full_like(Q, 0.1),
+                    np.full_like(Q, gap), 1 - Q, Q / 3], 1)
     with np.errstate(divide="ignore"):
         lg = np.log10(lin).astype(np.float32)
     got, st = gpu_forward(prob, log10_params=lg)
@@ -272,7 +323,15 @@ def test_ungapped_closed_form_150x300():
         logs = [np.sum(np.log10(np.where(rb == hb[j0:j0 + m], p[:, 5], p[:, 6]))) for j0 in range(n - m + 1)]
         top = max(logs)
         want = math.log10(p[0, 1] / n) + top + math.log10(sum(10 ** (x - top) for x in logs))
-        assert abs(got[k] - want) <= TOL32, (k, got[k], want)
+        if gap == 0.0:
+            assert abs(got[k] - want) <= TOL32, (k, got[k], want)
+            assert st[k] == binding.PAIR_FP64, (k, st[k])
+        elif r_idx[k] == h_idx[k]:
+            assert want > -10.0
+            assert abs(got[k] - want) <= TOL32, (k, got[k], want)
+            assert st[k] == binding.PAIR_FP32, (k, st[k], want)
+    if gap != 0.0:
+        check_against_oracle(prob, got, st, log10_params=lg)
 
 
 def test_explicit_log10_params():
