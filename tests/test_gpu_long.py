@@ -102,6 +102,33 @@ def test_long_read_row_outside_fp32_states_in_an_earlier_window():
     assert np.array_equal(st[~mine], st0[~mine])
 
 
+def test_long_read_explicit_alpha_zero_in_an_earlier_window():
+    """Explicit parameters with alpha = 0 on row 300 of a long read (the
+    FP32 rule evaluated in FP64 by the final window for the rows of earlier
+    windows): its pairs go to the FP64 sweep, no other pair changes status,
+    and every pair matches the oracle on the same parameters."""
+    prob = long_problem(seed=26)
+    par = oracle.params_from_phred(prob.base_qual, prob.ins_qual, prob.del_qual, prob.gcp_qual)
+    lg0 = np.log10(par).astype(np.float32)
+    got0, st0 = gpu_forward(prob, log10_params=lg0)
+    r_idx, _ = prob.pair_index()
+    m_all = np.diff(prob.read_offset)
+    cand = [r for r in range(prob.num_reads) if m_all[r] > 1024 and np.any(st0[r_idx == r] == binding.PAIR_FP32)]
+    assert cand, "no long read with a pair finished in FP32"
+    r = cand[0]
+    par[prob.read_offset[r] + 300, 0] = 0.0
+    with np.errstate(divide="ignore"):
+        lg = np.log10(par).astype(np.float32)
+    mine = r_idx == r
+    say(f"long read {r} (m = {m_all[r]}): explicit alpha = 0 on row 300, "
+        f"{int((st0[mine] == 0).sum())} FP32 pairs before")
+    got, st = gpu_forward(prob, log10_params=lg)
+    check_against_oracle(prob, got, st, log10_params=lg)
+    assert np.all(st[mine] != binding.PAIR_FP32)
+    assert np.all(st[mine & (st0 == binding.PAIR_FP32)] == binding.PAIR_FP64)
+    assert np.array_equal(st[~mine], st0[~mine])
+
+
 def test_maximum_read_length():
     """A read of 65,535 bases (the longest the plan takes: 64 windows of 1,024
     rows) against haplotypes of 1,000 and 1,700 bases, in explicit-parameter

@@ -272,6 +272,42 @@ def test_rows_outside_fp32_states():
         assert np.all(st[~flagged & inside] == binding.PAIR_FP32), st[~flagged & inside]
 
 
+def test_explicit_rows_outside_fp32_states():
+    """Explicit parameters (exponentiated in FP64, the FP32 rule evaluated in
+    FP64): alpha = 0 on an inner row, delta falling by 10^-8 from one row to
+    the next (kE near 10^8 eps > 2^20), and delta = 0 below a row with delta > 0
+    each send exactly their pairs to the FP64 sweep; alpha = 0 on the read's
+    first row (its M sum has no alpha) and delta falling by 10^-4 stay in
+    FP32.  Against the oracle on the same parameters."""
+    say("explicit rows outside the FP32 states")
+    prob = _ragged(45, [[20, 60, 150, 120, 63], [100, 90, 255, 31]], [[80, 200], [150, 300, 260]])
+    prob.gcp_qual[:] = 10
+    par = oracle.params_from_phred(prob.base_qual, prob.ins_qual, prob.del_qual, prob.gcp_qual)
+    off = prob.read_offset
+    par[off[0] + 0, 0] = 0.0        # alpha on the first row: not flagged
+    par[off[4] + 40, 0] = 0.0       # alpha = 0 inside: flagged
+    par[off[8] + 12, 2] *= 1e-8     # steep fall of delta: flagged
+    par[off[1] + 30, 2] = 0.0       # delta = 0: flagged
+    par[off[2] + 70, 2] *= 1e-4     # mild fall of delta: not flagged
+    with np.errstate(divide="ignore"):
+        lg = np.log10(par).astype(np.float32)
+    ref = oracle.forward(prob, log10_params=lg)
+    assert np.all(np.isfinite(ref))
+    r_idx, _ = prob.pair_index()
+    flagged = np.isin(r_idx, [4, 8, 1])
+    inside = ref > -60.0
+    say(f"  {int((flagged & inside).sum())} flagged and {int((~flagged & inside).sum())} other pairs in range")
+    assert (flagged & inside).sum() >= 4 and (~flagged & inside).sum() >= 6
+    assert (np.isin(r_idx, [0]) & inside).sum() >= 1 and (np.isin(r_idx, [2]) & inside).sum() >= 1
+    # default bins: the 20- and 31-base reads run in groups of 4 and 8 lanes
+    for kw in (dict(), dict(force_p=64, use_graph=False)):
+        got, st = gpu_forward(prob, log10_params=lg, **kw)
+        check_against_oracle(prob, got, st, ref=ref, log10_params=lg)
+        assert np.all(st[flagged] != binding.PAIR_FP32), st[flagged]
+        assert np.all(st[flagged & inside] == binding.PAIR_FP64), st[flagged & inside]
+        assert np.all(st[~flagged & inside] == binding.PAIR_FP32), st[~flagged & inside]
+
+
 def test_fp64_floor_status():
     """Unrelated 500-1023 base reads against random haplotypes fall below the
     FP64 sweep's range (scaled sum < 2^-1000, log10 L below about -608):
