@@ -205,10 +205,14 @@ void ph_plan_destroy(ph_plan *plan);
 typedef struct {
     int64_t max_subset_cells; /* cells (sum of m*n) per subset; a larger batch forms a
                                  subset of its own; <= 0 selects 2e10 */
+    int32_t buffer_sets;      /* device input/output buffer sets, reused in turn; 0: one per
+                                 subset when all of them take at most a quarter of the free
+                                 device memory (then no copy waits for compute), else 2;
+                                 values are clamped to 2 .. number of subsets */
     ph_plan_opts plan;        /* options of every subset's plan */
 } ph_pipeline_opts;
 
-typedef struct ph_pipeline ph_pipeline; /* opaque: subset plans, two device buffer sets, streams */
+typedef struct ph_pipeline ph_pipeline; /* opaque: subset plans, device buffer sets, streams */
 
 void ph_pipeline_opts_default(ph_pipeline_opts *opts);
 

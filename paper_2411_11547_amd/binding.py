@@ -53,7 +53,7 @@ class PhPlanOpts(ctypes.Structure):
 
 
 class PhPipelineOpts(ctypes.Structure):
-    _fields_ = [("max_subset_cells", ctypes.c_int64), ("plan", PhPlanOpts)]
+    _fields_ = [("max_subset_cells", ctypes.c_int64), ("buffer_sets", ctypes.c_int32), ("plan", PhPlanOpts)]
 
 
 class PHError(RuntimeError):
@@ -379,9 +379,10 @@ class Pipeline:
 
     DATA = ("read_bases", "base_qual", "ins_qual", "del_qual", "gcp_qual", "hap_bases")
 
-    def __init__(self, problem, max_subset_cells=0, pinned=True, tune_table=None, **plan_kw):
+    def __init__(self, problem, max_subset_cells=0, pinned=True, tune_table=None, buffer_sets=0, **plan_kw):
         opts = ph_pipeline_opts_default()
         opts.max_subset_cells = int(max_subset_cells)
+        opts.buffer_sets = int(buffer_sets)
         for k, v in plan_kw.items():
             setattr(opts.plan, k, v)
         # the same bin table as Plan, so that every pair gets the same lane

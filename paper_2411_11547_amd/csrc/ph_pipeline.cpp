@@ -6,11 +6,19 @@
 // (stage 7, per subset here so that the copies overlap the next subset's
 // compute).
 //
-// Streams: H2D copies on `h2d`, plans on `comp`, D2H copies on `d2h`; two
-// device buffer sets alternate between subsets.  Events order the reuse of a
-// buffer set: the H2D of subset k+2 waits until the compute of subset k has
-// read its inputs, and the compute of subset k+2 waits until the D2H of
-// subset k has read its outputs.
+// Streams: H2D copies on `h2d`, plans on `comp[k % 2]`, D2H copies on
+// `d2h`.  When every subset's inputs and outputs together take at most a
+// quarter of the free device memory (or the caller asks for as many buffer
+// sets as there are subsets), each subset gets its own buffer set and
+// the copies never wait for compute: all H2D copies are issued up front and
+// run back to back on the copy engine while the subsets compute.  Otherwise
+// N buffer sets (2 by default) are reused in turn, and events order their
+// reuse: the H2D of subset k+N waits until the compute of subset k has read
+// its inputs, and the compute of subset k+N waits until the D2H of subset k
+// has read its outputs.  (A copy that waits for a compute
+// event is released only when the kernels queued ahead of it on the shared
+// hardware queues drain, so with two sets the H2D of a subset cannot start
+// before the previous subset's sweeps end.)
 //
 // This file is a client of the public plan API plus the HIP runtime.
 #include <hip/hip_runtime.h>
@@ -78,8 +86,8 @@ struct ph_pipeline {
     int64_t P = 0, cells = 0;
     std::vector<Subset> subsets;
     int64_t max_rbases = 0, max_hbases = 0, max_pairs = 0;
-    BufSet set[2];
-    hipStream_t h2d = nullptr, comp = nullptr, d2h = nullptr;
+    std::vector<BufSet> sets;
+    hipStream_t h2d = nullptr, comp[2] = {nullptr, nullptr}, d2h = nullptr;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     bool timed = false;
 };
@@ -95,7 +103,7 @@ void destroy(ph_pipeline *q)
         for (void *b : bufs)
             if (b) (void)hipFree(b);
     }
-    for (auto &b : q->set) {
+    for (auto &b : q->sets) {
         void *bufs[] = {b.rb, b.bq, b.iq, b.dq, b.gq, b.hb, b.out, b.status};
         for (void *x : bufs)
             if (x) (void)hipFree(x);
@@ -103,7 +111,7 @@ void destroy(ph_pipeline *q)
         for (auto e : evs)
             if (e) (void)hipEventDestroy(e);
     }
-    hipStream_t ss[] = {q->h2d, q->comp, q->d2h};
+    hipStream_t ss[] = {q->h2d, q->comp[0], q->comp[1], q->d2h};
     for (auto s : ss)
         if (s) (void)hipStreamDestroy(s);
     if (q->t0) (void)hipEventDestroy(q->t0);
@@ -227,9 +235,19 @@ ph_status ph_pipeline_create(const ph_shape *shape, const ph_pipeline_opts *opts
         q->max_hbases = std::max(q->max_hbases, s.hb1 - s.hb0);
         q->max_pairs = std::max(q->max_pairs, s.pairs);
     }
-    const int nsets = q->subsets.size() > 1 ? 2 : 1;
+    // one buffer set per subset when they all fit well inside the free
+    // device memory, else two that alternate
+    int64_t all_bytes = 0;
+    for (const auto &s : q->subsets) all_bytes += 5 * (s.rb1 - s.rb0) + (s.hb1 - s.hb0) + 9 * s.pairs;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    const int nsub = (int)q->subsets.size();
+    int nsets = (nsub > 2 && all_bytes <= (int64_t)(free_b / 4)) ? nsub : 2;
+    if (opts.buffer_sets > 0) nsets = std::max(2, opts.buffer_sets);
+    nsets = std::min(nsets, nsub);
+    q->sets.resize(std::max(nsets, 1));
     for (int k = 0; k < nsets; ++k) {
-        BufSet &bs = q->set[k];
+        BufSet &bs = q->sets[k];
         if ((st = palloc(&bs.rb, q->max_rbases)) || (st = palloc(&bs.bq, q->max_rbases)) ||
             (st = palloc(&bs.iq, q->max_rbases)) || (st = palloc(&bs.dq, q->max_rbases)) ||
             (st = palloc(&bs.gq, q->max_rbases)) || (st = palloc(&bs.hb, q->max_hbases)) ||
@@ -248,7 +266,8 @@ ph_status ph_pipeline_create(const ph_shape *shape, const ph_pipeline_opts *opts
     }
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->h2d, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->comp, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->comp[0], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->comp[1], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->d2h, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&q->t0);
     if (e == hipSuccess) e = hipEventCreate(&q->t1);
@@ -282,11 +301,12 @@ ph_status ph_pipeline_forward(ph_pipeline *q, const ph_problem *hp, double *out_
         !hp->hap_bases)
         return pfail(PH_ERR_INVALID, "a host array is NULL");
     PCHK(hipEventRecord(q->t0, q->h2d));
-    for (size_t k = 0; k < q->subsets.size(); ++k) {
-        Subset &s = q->subsets[k];
-        BufSet &bs = q->set[k % 2];
+    const size_t nsub = q->subsets.size(), nsets = q->sets.size();
+    // stages 2 and 5: inputs of subset k, once subset k - nsets has read them
+    auto h2d = [&](size_t k) -> ph_status {
+        const Subset &s = q->subsets[k];
+        BufSet &bs = q->sets[k % nsets];
         const int64_t nrb = s.rb1 - s.rb0, nhb = s.hb1 - s.hb0;
-        // stages 2 and 5: inputs of subset k, once subset k-2 has read them
         if (bs.used) PCHK(hipStreamWaitEvent(q->h2d, bs.comp_done, 0));
         PCHK(hipMemcpyAsync(bs.rb, hp->read_bases + s.rb0, nrb, hipMemcpyHostToDevice, q->h2d));
         PCHK(hipMemcpyAsync(bs.bq, hp->base_qual + s.rb0, nrb, hipMemcpyHostToDevice, q->h2d));
@@ -295,26 +315,45 @@ ph_status ph_pipeline_forward(ph_pipeline *q, const ph_problem *hp, double *out_
         PCHK(hipMemcpyAsync(bs.gq, hp->gcp_qual + s.rb0, nrb, hipMemcpyHostToDevice, q->h2d));
         PCHK(hipMemcpyAsync(bs.hb, hp->hap_bases + s.hb0, nhb, hipMemcpyHostToDevice, q->h2d));
         PCHK(hipEventRecord(bs.h2d_done, q->h2d));
-        // stages 3 and 4: binning and sweeps of subset k, once its inputs
-        // are in and subset k-2's scores have left the output buffers
-        PCHK(hipStreamWaitEvent(q->comp, bs.h2d_done, 0));
-        if (bs.used) PCHK(hipStreamWaitEvent(q->comp, bs.d2h_done, 0));
+        return PH_OK;
+    };
+    // stages 3 and 4: binning and sweeps of subset k, once its inputs are in
+    // and subset k - nsets's scores have left the output buffers; stage 7,
+    // per subset: its scores back to the host
+    auto compute = [&](size_t k) -> ph_status {
+        Subset &s = q->subsets[k];
+        BufSet &bs = q->sets[k % nsets];
+        hipStream_t comp = q->comp[k % 2];
+        PCHK(hipStreamWaitEvent(comp, bs.h2d_done, 0));
+        if (bs.used) PCHK(hipStreamWaitEvent(comp, bs.d2h_done, 0));
         ph_problem dp{s.b1 - s.b0, s.d_bra, s.d_bha, s.r1 - s.r0, s.d_ro, bs.rb, bs.bq, bs.iq, bs.dq, bs.gq,
                       s.h1 - s.h0, s.d_ho, bs.hb};
-        ph_status st = ph_forward_batch(s.plan, &dp, nullptr, bs.out, bs.status, q->comp);
+        ph_status st = ph_forward_batch(s.plan, &dp, nullptr, bs.out, bs.status, comp);
         if (st != PH_OK) return st;
-        PCHK(hipEventRecord(bs.comp_done, q->comp));
-        // stage 7, per subset: scores back to the host
+        PCHK(hipEventRecord(bs.comp_done, comp));
         PCHK(hipStreamWaitEvent(q->d2h, bs.comp_done, 0));
         PCHK(hipMemcpyAsync(out_log10L + s.out0, bs.out, s.pairs * sizeof(double), hipMemcpyDeviceToHost, q->d2h));
         if (out_status)
             PCHK(hipMemcpyAsync(out_status + s.out0, bs.status, s.pairs, hipMemcpyDeviceToHost, q->d2h));
         PCHK(hipEventRecord(bs.d2h_done, q->d2h));
         bs.used = true;
+        return PH_OK;
+    };
+    ph_status st = PH_OK;
+    if (nsets == nsub) {
+        // a buffer set per subset: every H2D copy first, then the computes
+        for (size_t k = 0; k < nsub && st == PH_OK; ++k) st = h2d(k);
+        for (size_t k = 0; k < nsub && st == PH_OK; ++k) st = compute(k);
+    } else {
+        for (size_t k = 0; k < nsub && st == PH_OK; ++k) {
+            st = h2d(k);
+            if (st == PH_OK) st = compute(k);
+        }
     }
+    if (st != PH_OK) return st;
     PCHK(hipEventRecord(q->t1, q->d2h));
     PCHK(hipEventSynchronize(q->t1));
-    for (auto &bs : q->set) bs.used = false;
+    for (auto &bs : q->sets) bs.used = false;
     q->timed = true;
     return PH_OK;
 }

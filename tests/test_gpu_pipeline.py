@@ -31,15 +31,19 @@ def resident(prob):
     return res
 
 
-@pytest.mark.parametrize("cap_frac,pinned", [(0.13, True), (0.5, False), (0.0, True)])
-def test_pipeline_matches_resident_plan(cap_frac, pinned):
+@pytest.mark.parametrize("cap_frac,pinned,sets", [(0.13, True, 0), (0.13, True, 2), (0.13, True, 3),
+                                                 (0.5, False, 0), (0.0, True, 0)])
+def test_pipeline_matches_resident_plan(cap_frac, pinned, sets):
+    """sets = 0: one buffer set per subset (this problem fits); 2 and 3:
+    buffer sets reused in turn, with the copies waiting for compute."""
     prob = wl.config2(regions=40)
     cap = int(prob.total_cells * cap_frac)
     ref, ref_st = resident(prob)
-    pipe = binding.Pipeline(prob, max_subset_cells=cap, pinned=pinned)
-    say(f"pipeline: {prob.num_pairs} pairs, {pipe.num_subsets} subsets (cap {cap}), pinned={pinned}")
+    pipe = binding.Pipeline(prob, max_subset_cells=cap, pinned=pinned, buffer_sets=sets)
+    say(f"pipeline: {prob.num_pairs} pairs, {pipe.num_subsets} subsets (cap {cap}), pinned={pinned}, "
+        f"buffer sets {sets or 'auto'}")
     if cap_frac > 0:
-        assert pipe.num_subsets >= 2
+        assert pipe.num_subsets >= (4 if cap_frac < 0.2 else 2)
     assert pipe.num_pairs == prob.num_pairs and pipe.num_cells == prob.total_cells
     for rep in range(2):
         got, st = pipe.forward()
