@@ -242,7 +242,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
+        print(f"bench.py runs on one GPU only: the library has no multi-GPU path "
               f"(--gpus {args.gpus} requested). Each pair is independent, so sharding "
               f"would split regions across GPUs with no communication.", file=sys.stderr)
         sys.exit(2)

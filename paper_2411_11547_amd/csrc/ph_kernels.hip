@@ -391,7 +391,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
 {
     using C = Cfg<T, P, K>;
     static_assert(!W || (P == 64 && K * P == kLongRows), "windowed sweep: 64 lanes x kLongRows / 64 rows");
-    // rescaled states (M, Ih, Dh) for the FP32 sweeps
+    // rescaled states (M, It, Dh) for the FP32 sweeps
     constexpr bool HAT = sizeof(T) == 4;
     const int lane = threadIdx.x;
     const int g = lane / P;
@@ -633,7 +633,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
 #pragma unroll
     for (int r = 0; r < K; ++r) M[r] = I[r] = D[r] = 0;
     // row above the lane's first row at column j-1 = 0: the first lane's
-    // row-0 boundary (the edge value) sits in Ih (rescaled) or Dt (plain)
+    // row-0 boundary (the edge value) sits in It (rescaled) or Dt (plain)
     T Md = 0, Id = HAT ? edge : (T)0, Dd = HAT ? (T)0 : edge;
     // row-m sum (Viterbi: maximum).  Plain states: each 64-step chunk in T,
     // then FP64.  Rescaled states: the absorbing row's Dh, flushed into FP64

@@ -335,8 +335,9 @@ def config3(seed: int = 3, pairs: int = 50000) -> Problem:
 
 def config4(seed: int = 4, pairs: int = 10000) -> Problem:
     """Adjoint workload: independent pairs, haplotype = mutated reference of
-    n ~ U{200..600}; read = 150 bp of the unmutated reference with 1% errors;
-    Illumina-like base Q, ins/del U{40..45}, gcp 10."""
+    length U{200..600} (so 195..605 bases after an indel); read = 150 bp of
+    the unmutated reference with 1% errors; Illumina-like base Q, ins/del
+    U{40..45}, gcp 10."""
     rng = np.random.default_rng(seed)
     regs = []
     for _ in range(pairs):

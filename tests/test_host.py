@@ -1,0 +1,137 @@
+"""CPU checks of the host-side Python around the library: the seeded workload
+generators against their stated recipes and sizes, the autotuner's range
+table and the committed bin table, the benchmark's one-GPU guard, and the
+counter summaries that feed the benchmark's roofline traffic."""
+import os
+import sqlite3
+import subprocess
+import sys
+
+import numpy as np
+
+from paper_2411_11547_amd import tune
+from paper_2411_11547_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _common(p):
+    assert p.read_bases.max() <= 4 and p.hap_bases.max() <= 4
+    assert len(p.base_qual) == len(p.read_bases) == p.read_offset[-1]
+    assert len(p.hap_bases) == p.hap_offset[-1]
+    assert np.all(p.read_lengths >= 1) and np.all(p.hap_lengths >= 1)
+
+
+def test_config0_and_determinism():
+    a, b = wl.config0(), wl.config0()
+    _common(a)
+    assert a.num_pairs == 32 and np.all(a.read_lengths == 100)
+    for f in ("read_bases", "hap_bases", "base_qual", "ins_qual", "del_qual", "gcp_qual", "hap_offset"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+    assert np.all(a.ins_qual == 45) and np.all(a.del_qual == 45) and np.all(a.gcp_qual == 10)
+
+
+def test_uniform_batch_recipe():
+    p = wl.config1()
+    _common(p)
+    assert p.num_pairs == 512_000 and p.total_cells == 512_000 * 150 * 300
+    assert np.all(p.read_lengths == 150) and np.all(p.hap_lengths == 300)
+    assert p.ins_qual.min() >= 40 and p.ins_qual.max() <= 45 and np.all(p.gcp_qual == 10)
+    # Illumina-like base qualities: 60% Q37
+    assert abs(np.mean(p.base_qual == 37) - 0.60) < 0.01
+
+
+def test_mixed_batch_recipe():
+    p = wl.config2()
+    _common(p)
+    assert p.num_pairs == 3_757_266 and p.total_cells == 222_196_841_342
+    assert p.read_lengths.min() >= 50 and p.read_lengths.max() <= 250
+    assert p.hap_lengths.min() >= 100 and p.hap_lengths.max() <= 2000
+    haps_per_region = np.diff(p.batch_hap_begin)
+    assert haps_per_region.min() >= 1 and haps_per_region.max() <= 64
+    assert np.all(p.gcp_qual == 10)
+
+
+def test_precision_stress_and_adjoint_recipes():
+    p = wl.config3(pairs=2000)
+    _common(p)
+    assert p.num_pairs == 2000 and np.all(p.read_lengths == 250)
+    assert p.hap_lengths.min() >= 1000 and p.hap_lengths.max() <= 5000
+    q = wl.config4(pairs=500)
+    _common(q)
+    assert q.num_pairs == 500 and np.all(q.read_lengths == 150)
+    # reference length U{200..600}; the haplotype carries up to a 5-base indel
+    assert q.hap_lengths.min() >= 195 and q.hap_lengths.max() <= 605
+
+
+def test_tune_ranges_cover_every_read_length():
+    rs = tune.ranges()
+    assert rs[0][0] == 1 and rs[-1][1] == 1023
+    for (a0, a1), (b0, b1) in zip(rs, rs[1:]):
+        assert b0 == a1 + 1 and a0 <= a1
+    for lo, hi in rs:
+        # every range ends on a P*K - 1 boundary of some compiled configuration
+        assert any(p * k - 1 == hi for p, k in tune.CONFIGS) or hi % 4 == 3
+
+
+def test_committed_bin_table():
+    entries = []
+    with open(tune.DEFAULT_TABLE) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                entries.append(tuple(int(x) for x in line.split()))
+    assert entries, "empty table"
+    max_m = [e[0] for e in entries]
+    assert max_m == sorted(max_m) and len(set(max_m)) == len(max_m) and max_m[-1] == 1023
+    for m, p, k in entries:
+        assert (p, k) in tune.CONFIGS, (m, p, k)
+        assert p * k - 1 >= m, (m, p, k)  # the absorbing row fits
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def _fake_counter_db(path, rows):
+    con = sqlite3.connect(path)
+    con.execute("create table counters_collection (kernel_name text, counter_name text, value real, "
+                "dispatch_id integer, duration integer)")
+    con.executemany("insert into counters_collection values (?, ?, ?, ?, ?)", rows)
+    con.commit()
+    con.close()
+
+
+def test_profsum_traffic_scaling(tmp_path, capsys):
+    """Counters are scaled by (probe MiB) / (what the counter reads for the
+    probe copy); only forward FP32 sweep dispatches count."""
+    from paper_2411_11547_amd import profsum
+    sweep = "void ph::k_fwd32<16, 10, false>(ph::SweepArgs, int)"
+    vit = "void ph::k_fwd32<16, 10, true>(ph::SweepArgs, int)"
+    copy = "__amd_rocclr_copyBuffer"
+    fdb, wdb = str(tmp_path / "f.db"), str(tmp_path / "w.db")
+    # FETCH_SIZE reads half of the 1 MiB probe (512 KiB): scale 2
+    _fake_counter_db(fdb, [(sweep, "FETCH_SIZE", 100.0, 1, 10), (sweep, "FETCH_SIZE", 50.0, 2, 10),
+                           (vit, "FETCH_SIZE", 999.0, 3, 10), (copy, "FETCH_SIZE", 512.0, 4, 10)])
+    _fake_counter_db(wdb, [(sweep, "WRITE_SIZE", 30.0, 1, 10), (copy, "WRITE_SIZE", 1024.0, 2, 10)])
+    profsum.traffic(fdb, wdb, 1)
+    out = capsys.readouterr().out
+    line = [l for l in out.splitlines() if l.startswith("traffic_bytes_per_launch")][0]
+    want = (150.0 * 2.0 + 30.0 * 1.0) * 1024.0
+    assert abs(float(line.split(":")[1]) - want) <= 1e-6 * want
+
+
+def test_measured_traffic_needs_matching_sources(tmp_path, monkeypatch):
+    import bench
+    sha = bench.forward_sources_sha256()
+    assert len(sha) == 64 and int(sha, 16) >= 0
+    prof = tmp_path / "t.txt"
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
+    prof.write_text(f"# comment: x\ntraffic_bytes_per_launch: 1.5e9\nworkload: w1\nforward_sources_sha256: {sha}\n")
+    assert bench.measured_traffic("w1") == 1.5e9
+    assert bench.measured_traffic("w2") is None
+    prof.write_text("traffic_bytes_per_launch: 1.5e9\nworkload: w1\nforward_sources_sha256: 00\n")
+    assert bench.measured_traffic("w1") is None
