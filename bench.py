@@ -42,12 +42,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _code_tokens(text):
+    """C++ source with comments removed and whitespace collapsed, so that the
+    hash below changes with the code and not with its comments.  (String and
+    character literals in the kernel sources hold no comment markers.)"""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def forward_sources_sha256():
+    """Hash of the forward sweep's code (comments and layout ignored): the
+    HBM traffic measured for one version is reported only for that version."""
     import hashlib
     h = hashlib.sha256()
     for rel in FORWARD_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(_code_tokens(f.read()).encode())
     return h.hexdigest()
 
 

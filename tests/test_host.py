@@ -128,6 +128,9 @@ def test_measured_traffic_needs_matching_sources(tmp_path, monkeypatch):
     import bench
     sha = bench.forward_sources_sha256()
     assert len(sha) == 64 and int(sha, 16) >= 0
+    # comments and layout do not enter the hash; code does
+    assert bench._code_tokens("int a; // x\n/* y\n z */  int b;") == "int a; int b;"
+    assert bench._code_tokens("int a;") != bench._code_tokens("int b;")
     prof = tmp_path / "t.txt"
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
     prof.write_text(f"# comment: x\ntraffic_bytes_per_launch: 1.5e9\nworkload: w1\nforward_sources_sha256: {sha}\n")
