@@ -86,3 +86,37 @@ def test_viterbi_explicit_params_bounded_by_forward_and_graphs():
     sample = np.sort(rng.choice(prob.num_pairs, 300, replace=False))
     ref = oracle.viterbi(prob, log10_params=lg, pairs=sample)
     check_against_oracle(prob, v1, sv1, ref=ref, pairs=sample)
+
+
+def test_viterbi_rows_outside_fp32_states():
+    """The max-product sweep shares the forward's FP32 rule: rows with alpha
+    below 2^-20 (gap-open Phred 3 on insertion and deletion) or a gap-open
+    quality rising from Phred 2 to 90 send exactly their pairs to the FP64
+    sweep; gap-continuation Phred 0 rows (beta = 0) stay in FP32.  Default
+    bins (groups of 4, 8 and 16 lanes) and 64-lane groups."""
+    say("viterbi rows outside the FP32 states")
+    prob = _ragged(47, [[20, 60, 150, 120, 63], [100, 90, 255, 31]], [[80, 200], [150, 300, 260]])
+    prob.gcp_qual[:] = 10
+    off = prob.read_offset
+    for r, i in ((3, 119), (6, 89)):        # alpha < 0 on the last row
+        prob.ins_qual[off[r] + i] = 3
+        prob.del_qual[off[r] + i] = 3
+    for r, i in ((1, 1), (8, 30)):          # steep rise of the insertion gap-open quality
+        prob.ins_qual[off[r] + i - 1] = 2
+        prob.ins_qual[off[r] + i] = 90
+    prob.gcp_qual[off[4] + 10] = 0          # beta = 0: stays in FP32
+    prob.gcp_qual[off[0] + 5] = 0
+    ref = oracle.viterbi(prob)
+    assert np.all(np.isfinite(ref))
+    r_idx, _ = prob.pair_index()
+    flagged = np.isin(r_idx, [3, 6, 1, 8])
+    inside = ref > -60.0
+    say(f"  {int((flagged & inside).sum())} flagged and {int((~flagged & inside).sum())} other pairs in range")
+    assert (flagged & inside).sum() >= 4 and (~flagged & inside).sum() >= 4
+    assert (np.isin(r_idx, [0, 4]) & inside).sum() >= 2
+    for kw in (dict(), dict(force_p=64, use_graph=False)):
+        got, st = gpu_viterbi(prob, **kw)
+        check_against_oracle(prob, got, st, ref=ref)
+        assert np.all(st[flagged] != binding.PAIR_FP32), st[flagged]
+        assert np.all(st[flagged & inside] == binding.PAIR_FP64), st[flagged & inside]
+        assert np.all(st[~flagged & inside] == binding.PAIR_FP32), st[~flagged & inside]
