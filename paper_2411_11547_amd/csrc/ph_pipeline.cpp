@@ -7,7 +7,10 @@
 // compute).
 //
 // Streams: H2D copies on `h2d`, plans on `comp[k % 2]`, D2H copies on
-// `d2h`.  When every subset's inputs and outputs together take at most a
+// `d2h`.  Two compute streams let the start of subset k+1 (binning and the
+// first bins' sweeps) overlap the tail of subset k (44.3 -> 41.4 ms per call
+// on the mixed batch in 9 subsets).  When every subset's inputs and outputs
+// together take at most a
 // quarter of the free device memory (or the caller asks for as many buffer
 // sets as there are subsets), each subset gets its own buffer set and
 // the copies never wait for compute: all H2D copies are issued up front and
