@@ -39,7 +39,13 @@ namespace ph {
 void set_last_error(const char *msg);  // ph_api.cpp: the message of ph_last_error()
 }
 
+#ifndef PH_PIPE_COMP_STREAMS
+#define PH_PIPE_COMP_STREAMS 2
+#endif
+
 namespace {
+
+constexpr int kCompStreams = PH_PIPE_COMP_STREAMS;  // subsets alternate between these
 
 ph_status pfail(ph_status st, const char *fmt, ...)
 {
@@ -90,7 +96,7 @@ struct ph_pipeline {
     std::vector<Subset> subsets;
     int64_t max_rbases = 0, max_hbases = 0, max_pairs = 0;
     std::vector<BufSet> sets;
-    hipStream_t h2d = nullptr, comp[2] = {nullptr, nullptr}, d2h = nullptr;
+    hipStream_t h2d = nullptr, comp[kCompStreams] = {}, d2h = nullptr;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     bool timed = false;
 };
@@ -114,8 +120,10 @@ void destroy(ph_pipeline *q)
         for (auto e : evs)
             if (e) (void)hipEventDestroy(e);
     }
-    hipStream_t ss[] = {q->h2d, q->comp[0], q->comp[1], q->d2h};
+    hipStream_t ss[] = {q->h2d, q->d2h};
     for (auto s : ss)
+        if (s) (void)hipStreamDestroy(s);
+    for (auto s : q->comp)
         if (s) (void)hipStreamDestroy(s);
     if (q->t0) (void)hipEventDestroy(q->t0);
     if (q->t1) (void)hipEventDestroy(q->t1);
@@ -269,8 +277,8 @@ ph_status ph_pipeline_create(const ph_shape *shape, const ph_pipeline_opts *opts
     }
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->h2d, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->comp[0], hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->comp[1], hipStreamNonBlocking);
+    for (auto &c : q->comp)
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&c, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->d2h, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&q->t0);
     if (e == hipSuccess) e = hipEventCreate(&q->t1);
@@ -326,7 +334,7 @@ ph_status ph_pipeline_forward(ph_pipeline *q, const ph_problem *hp, double *out_
     auto compute = [&](size_t k) -> ph_status {
         Subset &s = q->subsets[k];
         BufSet &bs = q->sets[k % nsets];
-        hipStream_t comp = q->comp[k % 2];
+        hipStream_t comp = q->comp[k % kCompStreams];
         PCHK(hipStreamWaitEvent(comp, bs.h2d_done, 0));
         if (bs.used) PCHK(hipStreamWaitEvent(comp, bs.d2h_done, 0));
         ph_problem dp{s.b1 - s.b0, s.d_bra, s.d_bha, s.r1 - s.r0, s.d_ro, bs.rb, bs.bq, bs.iq, bs.dq, bs.gq,
