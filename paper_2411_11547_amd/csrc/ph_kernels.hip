@@ -444,7 +444,10 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     T ci[K], cd[K], ke[K];                // rescaled states (with ep)
     T edge = 0;
     bool bad = false;  // rescaled states: one of my rows is outside what they carry
-    if (sizeof(T) == 4 && !lin) {
+    bool phred32 = false;  // the FP32 sweep in Phred mode (rescaled states)
+    if constexpr (HAT) phred32 = lin == nullptr;
+    if (phred32) {
+      if constexpr (HAT) {
         // FP32 sweep, Phred mode: all of the lane's loads issued at once,
         // decoded through the FP32 tables (1 - p and p/3 rounded from FP64);
         // the transition parameters first, then the E table with each real
@@ -472,27 +475,16 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             const int i = base + r;
             const bool real = i < m;
             const float e = c_pf[gq[r]];
-            if constexpr (HAT) {
-                float f, c1, c2, k;
-                const bool ok = hat_coef(c_pf[iq[r]], c_pf[dq[r]], c_pf[iq[r + 1]], c_pf[dq[r + 1]], e,
-                                         c_1mpf[gq[r]], f, c1, c2, k);
-                const bool inner = real && i >= 1;
-                bad = bad || (inner && !ok);
-                fac[r] = inner ? f : 1.0f;
-                ci[r] = inner ? (T)c1 : i == 0 ? (T)1 : i == m ? (T)c_pf[iq[r]] : (T)0;
-                cd[r] = inner ? (T)c2 : (T)0;
-                ke[r] = inner ? (T)k : (T)0;
-                ep[r] = real ? (T)e : (i == m ? (T)1 : (T)0);
-            } else {
-                const float d = c_pf[iq[r + 1]], z = c_pf[dq[r + 1]];
-                fac[r] = 1.0f;
-                al[r] = real ? (T)(1.0f - d - z) : (T)0;
-                be[r] = real ? (T)c_1mpf[gq[r]] : (T)0;
-                de[r] = real ? (T)d : (i == m ? (T)1 : (T)0);
-                ep[r] = real ? (T)e : (T)1;
-                const float bn = c_1mpf[pb.gq[ro + min(i + 1, mload - 1)]];
-                zt[r] = (real && i + 1 < m) ? (T)(bn * z) : (T)0;
-            }
+            float f, c1, c2, k;
+            const bool ok = hat_coef(c_pf[iq[r]], c_pf[dq[r]], c_pf[iq[r + 1]], c_pf[dq[r + 1]], e,
+                                     c_1mpf[gq[r]], f, c1, c2, k);
+            const bool inner = real && i >= 1;
+            bad = bad || (inner && !ok);
+            fac[r] = inner ? f : 1.0f;
+            ci[r] = inner ? c1 : i == 0 ? 1.0f : i == m ? c_pf[iq[r]] : 0.0f;
+            cd[r] = inner ? c2 : 0.0f;
+            ke[r] = inner ? k : 0.0f;
+            ep[r] = real ? e : (i == m ? 1.0f : 0.0f);
         }
         if (t == 0 && m > 0 && r0 == 0) edge = ldexpf(c_1mpf[gq[0]], Range<T>::kExp) / (float)n;
 #pragma unroll
@@ -522,6 +514,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
                     *(double *)(mine + c * C::CODE_BYTES + q * 512) = v[0];
             }
         }
+      }
     } else {
         // FP64 sweep or explicit parameters: one row at a time in FP64, the
         // row parameters parked in the lane's own E entries, then loaded
