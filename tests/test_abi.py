@@ -98,3 +98,33 @@ def test_pipeline_shape_validation_errors():
     st = binding.load().ph_pipeline_create(ctypes.byref(shape), ctypes.byref(opts), ctypes.byref(h))
     assert st == -1 and "bad read or haplotype range" in binding.load().ph_last_error().decode()
     assert not h.value
+
+
+def test_struct_layout_matches_binding(tmp_path):
+    """Every struct the binding mirrors has the size and field offsets that a
+    C compiler gives the declarations in include/ph.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"ph_shape": binding.PhShape, "ph_problem": binding.PhProblem,
+               "ph_plan_opts": binding.PhPlanOpts, "ph_pipeline_opts": binding.PhPipelineOpts}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ph.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'    printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
