@@ -264,12 +264,19 @@ def test_rows_outside_fp32_states():
     assert (np.isin(r_idx, [3, 6]) & inside).sum() >= 3
     assert (np.isin(r_idx, list(mild)) & inside).sum() >= 2
     assert (np.isin(r_idx, [0]) & inside).sum() >= 1
-    for kw in (dict(), dict(force_p=64, use_graph=False)):
+    for kw in (dict(), dict(force_p=64, use_graph=False), dict(single_launch=True)):
         got, st = gpu_forward(prob, **kw)
         check_against_oracle(prob, got, st, ref=ref)
         assert np.all(st[flagged] != binding.PAIR_FP32), st[flagged]
         assert np.all(st[flagged & inside] == binding.PAIR_FP64), st[flagged & inside]
         assert np.all(st[~flagged & inside] == binding.PAIR_FP32), st[~flagged & inside]
+    # plain mode has no rescue: the flagged pairs are reported as unrescued
+    # FP32 results, never as good ones; the others match the oracle
+    got, st = gpu_forward(prob, plain=True, use_graph=False)
+    assert np.all(st[flagged] == binding.PAIR_FP32_UNRESCUED), st[flagged]
+    good = ~flagged & inside
+    assert np.all(st[good] == binding.PAIR_FP32), st[good]
+    assert np.max(np.abs(got[good] - ref[good])) <= TOL32
 
 
 def test_explicit_rows_outside_fp32_states():
