@@ -219,6 +219,15 @@ __device__ __forceinline__ void cell_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md
         acc += I[K - 1];
 }
 
+// Maximum of two non-negative floats (every max-product state and
+// coefficient of the rescaled sweep is >= 0): their bit patterns order like
+// unsigned integers, so the integer maximum needs none of the canonicalising
+// moves a float maximum gets for operands the compiler cannot prove canonical.
+__device__ __forceinline__ float max_nonneg(float a, float b)
+{
+    return __builtin_bit_cast(float, max(__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b)));
+}
+
 // The same step with the rescaled states (M, It, Dh) of the FP32 sweeps;
 // lam holds alpha_i lambda_ij, ci, cd, ke and ep the coefficients cI, cD, kE
 // and eps of the file header.  (eM, eI, eD) are added to the values received
@@ -233,7 +242,8 @@ __device__ __forceinline__ void cell_step(T (&M)[K], T (&I)[K], T (&D)[K], T &Md
 // received Dh needs no mask: it meets cD = 0 on the read's first row.
 //
 // Viterbi mode (V): every sum a maximum, as in cell_step; the rescaling by
-// positive per-row factors commutes with the maximum.
+// positive per-row factors commutes with the maximum, and every value is
+// non-negative (max_nonneg).
 template <typename T, int P, int K, bool W = false, bool V = false>
 __device__ __forceinline__ void cell_step_hat(T (&M)[K], T (&I)[K], T (&D)[K], T &Md, T &Id, T &Dd,
                                               const T *lam, const T (&ci)[K], const T (&cd)[K],
@@ -259,9 +269,9 @@ __device__ __forceinline__ void cell_step_hat(T (&M)[K], T (&I)[K], T (&D)[K], T
         const T mo = M[r], io = I[r], dol = D[r];
         T mn, in, dn;
         if constexpr (V) {
-            mn = lam[r] * fmax(fmax(mdg, ci[r] * idg), cd[r] * ddg);
-            in = fmax(mup, ke[r] * iup);
-            dn = fmax(mo, ep[r] * dol);
+            mn = lam[r] * max_nonneg(max_nonneg(mdg, ci[r] * idg), cd[r] * ddg);
+            in = max_nonneg(mup, ke[r] * iup);
+            dn = max_nonneg(mo, ep[r] * dol);
         } else {
             T x = fma(cd[r], ddg, mdg);
             x = fma(ci[r], idg, x);
