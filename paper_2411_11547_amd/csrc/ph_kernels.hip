@@ -490,7 +490,10 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
                                      c_1mpf[gq[r]], f, c1, c2, k);
             const bool inner = real && i >= 1;
             bad = bad || (inner && !ok);
-            fac[r] = inner ? f : 1.0f;
+            // a row outside the FP32 states gets zero emissions: its pair is
+            // recomputed in FP64, and every FP32 value stays >= 0 (alpha may
+            // be negative there), which the max-product sweep relies on
+            fac[r] = inner ? (ok ? f : 0.0f) : 1.0f;
             ci[r] = inner ? c1 : i == 0 ? 1.0f : i == m ? c_pf[iq[r]] : 0.0f;
             cd[r] = inner ? c2 : 0.0f;
             ke[r] = inner ? k : 0.0f;
@@ -544,6 +547,9 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
                 *slot(1, r) = inner ? (T)c2 : (T)0;
                 *slot(2, r) = inner ? (T)k : (T)0;
                 *slot(3, r) = real ? (T)p.e : (i == m ? (T)1 : (T)0);
+                // alpha folded into the row's emissions, zero on a row outside
+                // the FP32 states (as in the Phred branch)
+                *slot(4, r) = inner ? (ok ? (T)f : (T)0) : (T)1;
             } else {
                 const double bn = load_beta(pb, lin, ro + min(i + 1, mload - 1), c_prob);
                 *slot(0, r) = real ? (T)p.a : (T)0;
@@ -578,7 +584,8 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             const RowPar p = load_row(pb, lin, ro + ic, c_prob);
             const bool real = (r < K) && (i < m);
             const bool one = HAT && (r < K) && (i == m);
-            const double f = (HAT && i >= 1) ? p.a : 1.0;
+            // read before this row's entries are written
+            const double f = (HAT && real) ? (double)*slot(4, r) : 1.0;
             const uint32_t code = clamp_code(pb.read_bases[ro + ic]);
             const T lm = real ? (T)(p.lm * f) : (T)0, lx = real ? (T)(p.lx * f) : (T)0;
 #pragma unroll

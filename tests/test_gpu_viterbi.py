@@ -120,3 +120,31 @@ def test_viterbi_rows_outside_fp32_states():
         assert np.all(st[flagged] != binding.PAIR_FP32), st[flagged]
         assert np.all(st[flagged & inside] == binding.PAIR_FP64), st[flagged & inside]
         assert np.all(st[~flagged & inside] == binding.PAIR_FP32), st[~flagged & inside]
+
+
+def test_small_groups_next_to_rows_outside_fp32_states():
+    """Groups of 4 lanes: reads of 15 bases fill a 4 x 4 group, so a pair's
+    absorbing row is its group's last row, which the next group's first lane
+    receives through the lane shift.  Every other read has gap-open Phred 3
+    on its last row (alpha < 0, outside the FP32 states): those pairs go to
+    the FP64 sweep, and their neighbours in the same waves still finish in
+    FP32 and match the oracle, for the Viterbi score and the forward."""
+    from gpu_util import gpu_forward
+    say("groups of 4 lanes next to pairs outside the FP32 states")
+    prob = _ragged(49, [[15] * 12 + [14, 13]], [[40, 50, 60]])
+    prob.gcp_qual[:] = 10
+    off = prob.read_offset
+    flagged_reads = list(range(0, 12, 2))
+    for r in flagged_reads:
+        prob.ins_qual[off[r] + 14] = 3
+        prob.del_qual[off[r] + 14] = 3
+    r_idx, _ = prob.pair_index()
+    flagged = np.isin(r_idx, flagged_reads)
+    for run, ref in ((gpu_viterbi, oracle.viterbi(prob)), (gpu_forward, oracle.forward(prob))):
+        assert np.all(np.isfinite(ref))
+        inside = ref > -60.0
+        assert (flagged & inside).sum() >= 6 and (~flagged & inside).sum() >= 6
+        got, st = run(prob)
+        check_against_oracle(prob, got, st, ref=ref)
+        assert np.all(st[flagged & inside] == binding.PAIR_FP64), st[flagged & inside]
+        assert np.all(st[~flagged & inside] == binding.PAIR_FP32), st[~flagged & inside]
