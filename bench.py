@@ -28,6 +28,7 @@ FLOPS_PER_CELL = 11            # Eq. (1)-(3): 7 multiplications + 4 additions
 VALU_PER_CELL = 5              # FP32 instructions per cell of the rescaled-state sweep (4 FMA + 1 MUL)
 VITERBI_VALU_PER_CELL = 8      # the max-product cell: 5 MUL + 3 MAX
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector peak
+PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector peak
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes/clk x clock
 
 
@@ -178,6 +179,77 @@ def time_adjoint(steps, prob=None, dev=None):
             "frac_fp32_peak": round(ADJ_FLOPS_PER_CELL * cells / (kms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)}
 
 
+def single_table_file():
+    """The bin table of the single persistent launch (16 lanes x K = 3..16
+    rows, then 64 lanes x K = 5..16) as a tune-table file, so that both
+    launch modes can run the same bins."""
+    import tempfile
+    lines = [f"{16 * k - 1} 16 {k}" for k in range(3, 17)] + [f"{64 * k - 1} 64 {k}" for k in range(5, 17)]
+    f = tempfile.NamedTemporaryFile("w", suffix=".txt", delete=False)
+    f.write("\n".join(lines) + "\n")
+    f.close()
+    return f.name
+
+
+def launch_ab(prob, dev, steps):
+    """One persistent FP32 launch over every bin against one persistent
+    launch per bin (as concurrent graph branches), on the same bin table
+    (the single launch's: its kernel holds the 16-lane configurations)."""
+    from paper_2411_11547_amd import binding
+    path = single_table_file()
+    out = {"table": "16 lanes x 3..16 rows, then 64 lanes x 5..16 rows"}
+    try:
+        for mode in ("bins", "single"):
+            plan = binding.Plan(prob, tune_table=path, single_launch=mode == "single")
+            sec, st = time_forward(plan, dev, steps, 1)
+            plan.close()
+            out[mode] = {"gcups": round(prob.total_cells / sec / 1e9, 2),
+                         "fp32_sweep_ms": round(float(st.mean(axis=0)[1]), 4)}
+            log(f"launch A/B, {mode}: {sec * 1e3:.2f} ms/step, {prob.total_cells / sec / 1e9:.1f} GCUPS")
+    finally:
+        os.unlink(path)
+    return out
+
+
+def cpu_model():
+    """The host CPU's model name (as lscpu prints it), from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def frac_fp32(cells, ms, flops=FLOPS_PER_CELL):
+    return round(flops * cells / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)
+
+
+def uniform_report(steps=10, warmup=2):
+    """The uniform batch (1,000 regions x 64 reads of 150 bp x 8 haplotypes of
+    300 bp, 512,000 pairs, 2.304e10 cells): binned FP32 + FP64 rescue under
+    the graph, and the plain single-bin FP32 kernel, each with its FP32 sweep
+    stage against the FP32 vector peak (11 flops per cell)."""
+    from paper_2411_11547_amd import binding, workloads as wl
+    prob = wl.config1()
+    dev = binding.DeviceProblem(prob)
+    cells = prob.total_cells
+    rep = {"workload": prob.name, "pairs": prob.num_pairs, "cells": cells}
+    for name, kw in (("binned", {}), ("plain", {"plain": True, "use_graph": False})):
+        plan = binding.Plan(prob, **kw)
+        sec, st = time_forward(plan, dev, steps, warmup)
+        plan.close()
+        ms32 = float(st.mean(axis=0)[1])
+        rep[name] = {"gcups": round(cells / sec / 1e9, 2), "ms_per_step": round(sec * 1e3, 4),
+                     "fp32_sweep_ms": round(ms32, 4), "frac_fp32_peak": frac_fp32(cells, ms32)}
+        log(f"uniform {name}: {sec * 1e3:.3f} ms/step, {cells / sec / 1e9:.1f} GCUPS, "
+            f"FP32 stage {ms32:.3f} ms ({rep[name]['frac_fp32_peak']} of peak)")
+    rep["binned_vs_plain"] = round(rep["binned"]["gcups"] / rep["plain"]["gcups"], 3)
+    return rep
+
+
 def cpu_baseline(prob, target_cells=2.0e10, seed=0):
     import oracle
     r_idx, h_idx = prob.pair_index()
@@ -189,12 +261,12 @@ def cpu_baseline(prob, target_cells=2.0e10, seed=0):
     _, used = oracle.forward(prob, pairs=np.sort(take), return_threads=True)
     dt = time.perf_counter() - t0
     return {"value": round(sub_cells / dt / 1e9, 4), "unit": "GCUPS", "cores": int(used),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{len(take)} random pairs of the same batch ({sub_cells:.3e} cells, {dt:.1f} s), "
                       "FP64 full-matrix forward, gcc -O2"}
 
 
-def precision_report(steps=3):
+def precision_report(steps=5):
     """Precision stress workload (50,000 pairs, 250 bp reads, 1,000-5,000 bp
     haplotypes at 5-15% divergence, 30% low-quality reads, 2% N): forward
     GCUPS, rescue fraction and per-pair |d log10 L| against the FP64 oracle,
@@ -205,7 +277,7 @@ def precision_report(steps=3):
     prob = wl.config3()
     dev = binding.DeviceProblem(prob)
     plan = binding.Plan(prob)
-    sec, st = time_forward(plan, dev, steps, 1)
+    sec, st = time_forward(plan, dev, steps, 2)
     out, status = plan.forward(dev)
     torch.cuda.synchronize()
     got, status = out.cpu().numpy(), status.cpu().numpy()
@@ -214,10 +286,21 @@ def precision_report(steps=3):
     ref, used = oracle.forward(prob, return_threads=True)
     tor = time.perf_counter() - t0
     err = np.abs(got - ref)
+    cells_pair = prob.pair_cells()
+    resc_cells = int(cells_pair[status != 0].sum())
+    ms64 = float(st.mean(axis=0)[2])
     rep = {"workload": prob.name, "pairs": prob.num_pairs, "cells": prob.total_cells,
-           "gcups": round(prob.total_cells / sec / 1e9, 2),
-           "stage_ms": {"fp32_sweep": round(float(st.mean(axis=0)[1]), 3),
-                        "fp64_rescue": round(float(st.mean(axis=0)[2]), 3)},
+           "gcups": round(prob.total_cells / sec / 1e9, 2), "ms_per_step": round(sec * 1e3, 3),
+           "stage_ms": {"binning": round(float(st.mean(axis=0)[0]), 3),
+                        "fp32_sweep": round(float(st.mean(axis=0)[1]), 3),
+                        "fp64_rescue": round(ms64, 3)},
+           "rescue_fraction": round(float((status != 0).mean()), 4),
+           "fp64_rescue_stage": {"cells": resc_cells,
+                                 "gcups": round(resc_cells / (ms64 * 1e-3) / 1e9, 2),
+                                 "tflops": round(FLOPS_PER_CELL * resc_cells / (ms64 * 1e-3) / 1e12, 3),
+                                 "peak": PEAK_FP64_TFLOPS,
+                                 "frac_fp64_peak": round(FLOPS_PER_CELL * resc_cells / (ms64 * 1e-3) / 1e12
+                                                         / PEAK_FP64_TFLOPS, 4)},
            "oracle_s": round(tor, 1), "oracle_threads": int(used),
            "log10L_range": [round(float(ref.min()), 2), round(float(ref.max()), 2)]}
     for name, code in (("fp32", 0), ("fp64", 1), ("fp64_floor", 2)):
@@ -226,7 +309,9 @@ def precision_report(steps=3):
         rep[name] = {"pairs": int(sel.sum()), "fraction": round(float(sel.mean()), 4),
                      "max_abs_dlog10L": float(e.max()) if e.size and code != 2 else None,
                      "p99_abs_dlog10L": float(np.percentile(e, 99)) if e.size and code != 2 else None}
-    log(json.dumps(rep))
+    log(f"precision stress: {rep['gcups']} GCUPS, rescued {rep['rescue_fraction']}, FP64 stage "
+        f"{rep['fp64_rescue_stage']['frac_fp64_peak']} of the FP64 peak; FP32 max |d| "
+        f"{rep['fp32']['max_abs_dlog10L']}, FP64 max |d| {rep['fp64']['max_abs_dlog10L']}")
     return rep
 
 
@@ -251,6 +336,9 @@ def main():
     ap.add_argument("--precision", action="store_true",
                     help="only run the precision-stress report (all pairs against the oracle)")
     ap.add_argument("--adjoint-steps", type=int, default=5)
+    ap.add_argument("--no-uniform", action="store_true", help="skip the uniform-batch report")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision-stress report")
+    ap.add_argument("--no-adjoint-mixed", action="store_true", help="skip the adjoint on the mixed batch")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -289,6 +377,8 @@ def main():
         vstat = torch.empty(max(plan.num_pairs, 1), dtype=torch.uint8, device="cuda")
         vsec, vst = time_forward_fn(lambda: plan.viterbi(dev, out=vout, status=vstat), plan, 3, 1)
         viterbi = {"gcups": round(cells / vsec / 1e9, 2), "ms_per_step": round(vsec * 1e3, 3),
+                   # 7 multiplications and 4 maxima per cell (Eq. (1)-(3) with every sum a maximum)
+                   "frac_fp32_peak": frac_fp32(cells, float(vst.mean(axis=0)[1])),
                    "stage_ms": {"binning": round(float(vst.mean(axis=0)[0]), 4),
                                 "fp32_sweep": round(float(vst.mean(axis=0)[1]), 4),
                                 "fp64_rescue": round(float(vst.mean(axis=0)[2]), 4)},
@@ -298,19 +388,14 @@ def main():
 
     other = None
     if not args.no_ab:
-        mode = "bins" if args.launch == "single" else "single"
-        oplan = binding.Plan(prob, tune_table=args.tune_table, single_launch=mode == "single")
-        osec, ost = time_forward(oplan, dev, max(2, args.steps // 2), 1)
-        other = {"launch": mode, "gcups": round(cells / osec / 1e9, 2),
-                 "fp32_sweep_ms": round(float(ost.mean(axis=0)[1]), 4)}
-        log(f"{mode}: {osec * 1e3:.2f} ms/step, {cells / osec / 1e9:.1f} GCUPS")
-        oplan.close()
+        other = launch_ab(prob, dev, max(2, args.steps // 2))
 
     plain = None
     if not args.no_plain:
         pplan = binding.Plan(prob, plain=True, use_graph=False)
         psec, pst = time_forward(pplan, dev, args.plain_steps, 1)
         plain = cells / psec / 1e9
+        plain_ms32 = float(pst.mean(axis=0)[1])
         log(f"plain: {psec * 1e3:.2f} ms/step, {plain:.1f} GCUPS")
         pplan.close()
 
@@ -322,8 +407,11 @@ def main():
             "kernel_ms": round(float(st_mean[1]), 4),
             "valu_slot_frac": round(VALU_PER_CELL * cells / t32 / PEAK_VALU_LANE_OPS, 4)}
 
+    uniform = None if args.no_uniform else uniform_report()
+    precision = None if args.no_precision else precision_report()
     adj = None if args.no_adjoint else time_adjoint(args.adjoint_steps)
-    adj_mixed = None if args.no_adjoint else time_adjoint(max(1, args.adjoint_steps // 2), prob, dev)
+    adj_mixed = None if args.no_adjoint or args.no_adjoint_mixed else \
+        time_adjoint(max(1, args.adjoint_steps // 2), prob, dev)
     e2e = None if args.no_e2e else time_pipeline(prob)
 
     cpu = None if args.no_cpu else cpu_baseline(prob)
@@ -338,6 +426,7 @@ def main():
                       "read_len": read_len, "hap_len": hap_len, "graph": True,
                       "fp32_launch": args.launch},
            "plain_gcups": None if plain is None else round(plain, 2),
+           "plain_frac_fp32_peak": None if plain is None else frac_fp32(cells, plain_ms32),
            "binned_vs_plain": None if plain is None else round(gcups / plain, 3),
            "rescued_pairs": int(rescued),
            "launch": args.launch, "other_launch": other,
@@ -348,6 +437,8 @@ def main():
            "adjoint": adj,
            "adjoint_mixed": adj_mixed,
            "end_to_end_host_input": e2e,
+           "uniform": uniform,
+           "precision_stress": precision,
            "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     if args.copy_probe_mib:

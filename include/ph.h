@@ -123,13 +123,20 @@ typedef struct ph_plan ph_plan; /* opaque: owns scratch, queues, checkpoints, gr
 /* Fill opts with defaults. */
 void ph_plan_opts_default(ph_plan_opts *opts);
 
-/* Build a plan for problems of the given shape (HOST arrays, read once).
+/* Build a plan for problems of the given shape (HOST arrays, read once):
+ * the partitioning of the pairs by read length into (lanes per pair, rows
+ * per lane) configurations, each with its own work list (Section III-C),
+ * and the scratch of the on-device sorting of a batch list into those lists
+ * (Section III-A, stage 3).  This is the `ph_plan` call of the library's
+ * call list, named ph_plan_create because C cannot give a function the name
+ * of the ph_plan type.
  * Validates the shape: batch ranges inside the read/haplotype counts, every
  * read and haplotype non-empty (PH_ERR_INVALID), every read at most 65535
  * bases (PH_ERR_UNSUPPORTED; plain mode: 1023); then sizes and allocates
  * device scratch on the current device.  Reads of up to 1023 bases are
  * binned by length; longer reads are swept in windows of 1024 rows whose
  * boundary rows (3 values per haplotype column) live in plan scratch.
+ * The plan owns its scratch, streams and graphs until ph_plan_destroy.
  * *out receives the plan. */
 ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts, ph_plan **out);
 
@@ -162,25 +169,30 @@ ph_status ph_viterbi_batch(ph_plan *plan, const ph_problem *problem,
  * receives d(sum_p u_p log10 L_p)/d log10 theta for the seven parameters of
  * every read base, u = grad_log10L[P] (device, double).  The derivative of
  * Eq. (1)-(4) run backwards; d log10 L / d log10 theta is the posterior
- * expected number of uses of theta.  The call runs its own checkpointed FP32
- * forward (every lane's state, i.e. every K-th row, every 8 columns) and
- * then the reverse sweep, so it needs no preceding forward call.  Pairs
+ * expected number of uses of theta.  The call is self-contained: it runs its
+ * own checkpointed FP32 forward (every lane's state, i.e. every K-th row,
+ * at a fixed interval of columns) and then the reverse sweep, so it needs no
+ * preceding ph_forward_batch and keep_checkpoints only moves the set-up of
+ * its tables to plan creation (the forward call's own scores are not
+ * reused: the adjoint's lane layout differs from the forward's bins).  Pairs
  * whose scaled FP32 sum falls below the plan's rescue threshold (or
  * overflows), or with a read row below the first whose beta is below 2^-20
  * (the adjoint's rescaled states divide by beta; Phred gap continuation 0
  * gives beta = 0), are redone in FP64; only pairs below the
  * FP64 floor (log10 L < about -608) get NaN gradients, and pairs with
  * u_p = 0 contribute nothing.  The gradient buffer is overwritten.  Reads
- * longer than 319 bases give PH_ERR_UNSUPPORTED.  Sums over pairs sharing a
- * read use float atomics, so the last bits of a gradient may depend on
- * completion order. */
+ * longer than 319 bases give PH_ERR_UNSUPPORTED.  Deterministic: each pair
+ * writes its own gradient rows, and the rows of a read with several pairs
+ * are summed in haplotype order in FP64, so replays give identical bits. */
 ph_status ph_backward_batch(ph_plan *plan, const ph_problem *problem,
                             const float *log10_params, const double *grad_log10L,
                             float *grad_params, void *stream);
 
 /* Check the device data of a problem against the plan: every base code in
  * 0..4.  Synchronous; PH_ERR_INVALID if a code is out of range.  The forward
- * pass itself does not read-validate device data. */
+ * pass itself does not read-validate device data: the kernels read codes
+ * above 4 as N.  Uses a counter of its own, so the bookkeeping of the last
+ * forward call (ph_plan_rescued) is left as it was. */
 ph_status ph_validate(ph_plan *plan, const ph_problem *problem, void *stream);
 
 /* Kernel-level timing of the most recent ph_forward_batch / ph_backward_batch
@@ -189,7 +201,9 @@ ph_status ph_validate(ph_plan *plan, const ph_problem *problem, void *stream);
  * ms[3] = adjoint sweep.  Synchronises the stream. */
 ph_status ph_plan_stage_ms(ph_plan *plan, float ms[4]);
 
-/* Number of pairs sent to the FP64 sweep by the most recent forward call
+/* Number of pairs sent to an FP64 sweep by the most recent forward call,
+ * those of reads longer than 1023 bases (windowed sweep) included; equal to
+ * the number of pairs with status PH_PAIR_FP64 or PH_PAIR_FP64_FLOOR
  * (synchronises the stream). */
 ph_status ph_plan_rescued(ph_plan *plan, int64_t *count);
 
@@ -242,7 +256,9 @@ void ph_pipeline_destroy(ph_pipeline *pipe);
 void *ph_host_alloc(size_t bytes);
 void ph_host_free(void *ptr);
 
-/* Message of the calling thread's most recent failure ("" if none). */
+/* Message of the calling thread's most recent failure ("" if none).  It
+ * takes no plan: the message is kept per thread, so it also covers calls
+ * that failed before a plan existed (ph_plan_create, ph_pipeline_create). */
 const char *ph_last_error(void);
 
 /* Library version string. */

@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpairhmm.so")
+# the library this process loads: libpairhmm.so next to this file, unless
+# PAIRHMM_LIBRARY names another build of it (e.g. libpairhmm_ftz.so)
+LIB_PATH = os.environ.get("PAIRHMM_LIBRARY") or os.path.join(HERE, "libpairhmm.so")
 # bin table measured by tune.py on MI355X; "builtin" selects the library's own
 TUNED_TABLE = os.path.join(HERE, "tune_gfx950.txt")
 
@@ -303,7 +305,10 @@ class Plan:
         opts.force_p = int(force_p)
         opts.keep_checkpoints = int(bool(keep_checkpoints))
         opts.single_launch = int(bool(single_launch))
-        if tune_table is None and not force_p and os.path.exists(TUNED_TABLE):
+        # the tuned table by default; the single persistent launch takes only
+        # 16-lane bins, so it gets the library's built-in table for it unless
+        # a table is given
+        if tune_table is None and not force_p and not single_launch and os.path.exists(TUNED_TABLE):
             tune_table = TUNED_TABLE
         if tune_table == "builtin":
             tune_table = None

@@ -48,6 +48,12 @@
 #include "ph_device.h"
 #include "ph_internal.h"
 
+// 1: the reverse sweep prefetches the next block's checkpoint into registers
+// (configurations where that does not spill)
+#ifndef PH_ADJ_PREFETCH
+#define PH_ADJ_PREFETCH 1
+#endif
+
 namespace ph {
 
 __constant__ double c_prob[256];  // Phred q -> 10^(-q/10), computed on the host in FP64
@@ -403,11 +409,14 @@ __device__ __forceinline__ void adj_load_ck(const T *ck, int q, int lane, T (&cq
     for (int v = 0; v < V; ++v) cq[v] = c0[v * 64];
 }
 
-// Seven row sums of forward value x backward value, per row of the lane:
-// alpha, beta, mismatch emission, delta, eps (insert), eps (delete), zeta.
+// Eight row sums of forward value x backward value, per row of the lane:
+// alpha, beta, mismatch emission, match emission, delta, eps (insert),
+// eps (delete), zeta.  The match and mismatch emission uses are summed
+// separately (not the match uses as alpha + beta - mismatch uses, which
+// cancels on rows where nearly every probable alignment mismatches).
 template <typename T, int K>
 struct AdjSums {
-    T a[K], b[K], x[K], d[K], ei[K], ed[K], z[K];
+    T a[K], b[K], x[K], mt[K], d[K], ei[K], ed[K], z[K];
 };
 
 // Reverse wavefront over the checkpointed forward of the wave's pairs.
@@ -459,14 +468,18 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
     for (int r = 0; r < K; ++r) {
         BI[r] = BL[r] = (T)0;
         BD[r] = (HAT && r == pr.rml) ? bscale : (T)0;
-        A.a[r] = A.b[r] = A.x[r] = A.d[r] = A.ei[r] = A.ed[r] = A.z[r] = (T)0;
+        A.a[r] = A.b[r] = A.x[r] = A.mt[r] = A.d[r] = A.ei[r] = A.ed[r] = A.z[r] = (T)0;
     }
     T bl_dn_prev = 0;
 
     const int NB = S / CB;  // fine blocks; the checkpoint of block b is b / R
+    // The checkpoint of the next block is prefetched into registers during
+    // the current one, except where those registers would spill.
+    constexpr bool PREFETCH = PH_ADJ_PREFETCH && (K < 5 || CB < 4 || sizeof(T) == 8);
     T cn[V];
-    adj_load_ck<T, K>(ck, (NB - 1) / R, pr.lane, cn);
+    if constexpr (PREFETCH) adj_load_ck<T, K>(ck, (NB - 1) / R, pr.lane, cn);
     for (int b = NB - 1; b >= 0; --b) {
+        if constexpr (!PREFETCH) adj_load_ck<T, K>(ck, b / R, pr.lane, cn);
         const int q = b;  // steps of this block: q CB .. q CB + CB - 1
         // F[c]: lane state before step q CB + c; bb[c]: the values received
         // from the lane above at step q CB + c - 1 (bb[0]: from the checkpoint)
@@ -478,7 +491,7 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
             for (int r = 0; r < K; ++r) F[0][v][r] = cn[v * K + r];
             bb[0][v] = cn[3 * K + v];
         }
-        if (b > 0) adj_load_ck<T, K>(ck, (b - 1) / R, pr.lane, cn);
+        if (PREFETCH && b > 0) adj_load_ck<T, K>(ck, (b - 1) / R, pr.lane, cn);
 
         if constexpr (R > 1) {
             // advance from the checkpoint at step (b / R) R CB to step q CB
@@ -558,7 +571,11 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
                     A.b[r] = fma(fma(pr.cd[r], ddg, idg), bl, A.b[r]);  // (Ih + cD Dh)_diag Bl
                 else
                     A.b[r] = fma(fma(pr.be[r], idg, ddg), bl, A.b[r]);  // (beta I + D')_diag Bl
-                A.x[r] = fma(w[r] * F[c + 1][0][r], bm, A.x[r]);
+                // M(i,j) B_M(i,j) into the mismatch or the match sum (w is 0 or 1,
+                // so both factors are exact)
+                const T wf = w[r] * F[c + 1][0][r];
+                A.x[r] = fma(wf, bm, A.x[r]);
+                A.mt[r] = fma(F[c + 1][0][r] - wf, bm, A.mt[r]);
                 A.d[r] = fma(mu, bi, A.d[r]);
                 A.ei[r] = fma(iu, bi, A.ei[r]);
                 A.ed[r] = fma(F[c][2][r], bd, A.ed[r]);
@@ -574,12 +591,20 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
     }
 }
 
-// Expected uses per row, g = coefficient x sum / (L_s 2^SB) (lam_match by
-// alpha + beta uses - mismatch uses), times the pair's upstream gradient u,
-// added into the per-read-base gradient array.  The coefficient is the one
-// the sum's backward value multiplies in the DP: FP32 alpha, kD (delta's),
-// kE and eps (eps's two terms), 1 (zeta's: M -> Dh has a unit coefficient);
-// FP64 alpha, delta, eps, zeta'.  beta's sum already holds beta.
+// Destination of row i of the pair's gradient: the read's own row when the
+// read has no other pair, else the pair's row of the per-pair array.
+template <typename T, int P, int K>
+__device__ __forceinline__ float *adj_row(const AdjArgs &A, const AdjPair<T, P, K> &pr, int i)
+{
+    return pr.rec.direct ? A.grad_out + (pr.ro + i) * 7 : A.grad_pair + (pr.rec.grow + i) * 7;
+}
+
+// Expected uses per row, g = coefficient x sum / (L_s 2^SB), times the
+// pair's upstream gradient u, stored (plain stores: every row has one
+// writer) at the pair's rows.  The coefficient is the one the sum's backward
+// value multiplies in the DP: FP32 alpha, kD (delta's), kE and eps (eps's
+// two terms), 1 (zeta's: M -> Dh has a unit coefficient); FP64 alpha,
+// delta, eps, zeta'.  beta's sum already holds beta.
 template <typename T, int P, int K>
 __device__ __forceinline__ void adj_emit(const AdjArgs &A, const AdjPair<T, P, K> &pr, double u, double inv,
                                          const AdjSums<T, K> &s)
@@ -591,6 +616,7 @@ __device__ __forceinline__ void adj_emit(const AdjArgs &A, const AdjPair<T, P, K
         const double ga = (double)pr.al[r] * (double)s.a[r] * inv;
         const double gb = (double)s.b[r] * inv;
         const double gx = (double)s.x[r] * inv;
+        const double gm = (double)s.mt[r] * inv;
         double gd, ge, gz;
         if constexpr (AdjPair<T, P, K>::HAT) {
             gd = (double)pr.kd[r] * (double)s.d[r] * inv;
@@ -601,14 +627,28 @@ __device__ __forceinline__ void adj_emit(const AdjArgs &A, const AdjPair<T, P, K
             ge = (double)pr.ep[r] * ((double)s.ei[r] + (double)s.ed[r]) * inv;
             gz = (double)pr.ze[r] * (double)s.z[r] * inv;
         }
-        float *o = A.grad_out + (pr.ro + i) * 7;
-        atomicAdd(o + 0, (float)(u * ga));
-        atomicAdd(o + 1, (float)(u * gb));
-        atomicAdd(o + 2, (float)(u * gd));
-        atomicAdd(o + 3, (float)(u * ge));
-        atomicAdd(o + 4, (float)(u * gz));
-        atomicAdd(o + 5, (float)(u * (ga + gb - gx)));
-        atomicAdd(o + 6, (float)(u * gx));
+        float *o = adj_row<T, P, K>(A, pr, i);
+        o[0] = (float)(u * ga);
+        o[1] = (float)(u * gb);
+        o[2] = (float)(u * gd);
+        o[3] = (float)(u * ge);
+        o[4] = (float)(u * gz);
+        o[5] = (float)(u * gm);
+        o[6] = (float)(u * gx);
+    }
+}
+
+// A pair with upstream gradient 0 contributes zeros (whatever its range).
+template <typename T, int P, int K>
+__device__ __forceinline__ void adj_emit_zero(const AdjArgs &A, const AdjPair<T, P, K> &pr)
+{
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const int i = pr.t * K + r;
+        if (i >= pr.m) continue;
+        float *o = adj_row<T, P, K>(A, pr, i);
+#pragma unroll
+        for (int c = 0; c < 7; ++c) o[c] = 0.0f;
     }
 }
 
@@ -643,7 +683,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PH_ADJ_WAVES
         AdjSums<float, K> sums;
         adj_backward<float, P, K, kAdjC, kAdjR>(pr, ck, good ? ldexpf(1.f, SB) : 0.f, sums);
         const double u = valid ? A.grad_in[rec.out] : 0.0;
-        if (u != 0.0) {  // a pair with u = 0 contributes nothing, whatever its range
+        if (!valid) {
+            // a group past the end of the records mirrors group 0: no output
+        } else if (u == 0.0) {  // a pair with u = 0 contributes nothing, whatever its range
+            adj_emit_zero<float, P, K>(A, pr);
+        } else {
             if (good) {
                 adj_emit<float, P, K>(A, pr, u, 1.0 / ldexp(Ls, SB), sums);
             } else if (pr.t == 0) {
@@ -688,6 +732,31 @@ __global__ __launch_bounds__(64) void k_adj64(AdjArgs A)
         adj_emit<double, P, K>(A, pr, A.grad_in[rec.out], good ? 1.0 / ldexp(Ls, SB) : (double)NAN, sums);
         __syncthreads();  // LDS tables are rebuilt for the next pair
     }
+}
+
+// Fixed-order sum over the pairs of each read with several pairs:
+// grad_out[ro + i][c] = sum over h = 0 .. H-1 of grad_pair[grow + h m + i][c],
+// accumulated in FP64 in haplotype order, so the result does not depend on
+// which pair finished first.  One workgroup per read.
+__global__ __launch_bounds__(256) void k_adj_reduce(const AdjRedRead *reads, const float *gp, float *go)
+{
+    const AdjRedRead rd = reads[blockIdx.x];
+    const int64_t n = (int64_t)rd.m * 7;
+    const float *src = gp + rd.grow * 7;
+    float *dst = go + rd.ro * 7;
+    for (int64_t e = threadIdx.x; e < n; e += 256) {
+        double s = 0.0;
+        for (int h = 0; h < rd.H; ++h) s += (double)src[(int64_t)h * n + e];
+        dst[e] = (float)s;
+    }
+}
+
+hipError_t launch_adj_reduce(const AdjRedRead *reads, int32_t nreads, const float *grad_pair, float *grad_out,
+                             hipStream_t s)
+{
+    if (nreads <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_reduce, dim3(nreads), dim3(256), 0, s, reads, grad_pair, grad_out);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_zero_f32(float *p, int64_t n)

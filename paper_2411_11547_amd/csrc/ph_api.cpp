@@ -151,7 +151,7 @@ struct ph_plan {
     std::vector<int64_t> bin_pairs;    // pairs per bin (host count)
     std::vector<int> bin_grid;         // persistent grid per bin (0 = empty)
     int64_t class_pairs[kRescueClasses] = {0, 0, 0, 0};
-    int rescue_grid[kRescueClasses] = {0, 0, 0, 0};
+    int rescue_grid[2][kRescueClasses] = {};  // [rescaled FP64, plain FP64] per class
     int plain_K = 0, plain_grid = 0;
     // reads longer than kMaxReadLen: one extra bin swept in windows
     int long_bin = -1, windows = 0, long_grid = 0, long64_grid = 0;
@@ -168,6 +168,7 @@ struct ph_plan {
     int32_t *d_hist = nullptr;
     PairRec *d_recs = nullptr;
     Book *d_book = nullptr;
+    int32_t *d_bad = nullptr;          // ph_validate: count of base codes above 4
     int32_t *d_rescue = nullptr;
     double *d_lin = nullptr;
     int64_t lin_cap = 0;
@@ -205,6 +206,12 @@ struct ph_plan {
     std::vector<AdjRun> adj_runs;
     AdjRec *d_adj_recs = nullptr;
     float *d_ws = nullptr;
+    // gradients of reads with several pairs: per-pair rows, then a
+    // fixed-order sum per read (no float atomics)
+    float *d_grad_pair = nullptr;
+    AdjRedRead *d_red = nullptr;
+    int32_t n_red = 0;
+    bool adj_zero = false;  // some read has no pair: its rows are zeroed
     int32_t *d_adj_ctr = nullptr;  // [2][kAdj64Classes] FP64 queue lengths, cursors; then one cursor per run
     // FP64 pass over the pairs the FP32 pass leaves out: queues per class,
     // [2][kAdj64Classes] counters (lengths, cursors), per-workgroup checkpoints
@@ -232,9 +239,9 @@ void free_plan(ph_plan *p)
         }
     if (p->adj_exec) (void)hipGraphExecDestroy(p->adj_exec);
     if (p->adj_graph) (void)hipGraphDestroy(p->adj_graph);
-    void *bufs[] = {p->d_out_offset, p->d_m2bin, p->d_bin_G, p->d_hist, p->d_recs, p->d_book, p->d_rescue, p->d_lin,
+    void *bufs[] = {p->d_out_offset, p->d_m2bin, p->d_bin_G, p->d_hist, p->d_recs, p->d_book, p->d_bad, p->d_rescue, p->d_lin,
                     p->d_bnd32, p->d_bnd64, p->d_long_rescue,
-                    p->d_adj_recs, p->d_ws, p->d_adj_ctr, p->d_q64, p->d_ws64};
+                    p->d_adj_recs, p->d_ws, p->d_adj_ctr, p->d_q64, p->d_ws64, p->d_grad_pair, p->d_red};
     for (auto &e : p->ev_adj)
         if (e) (void)hipEventDestroy(e);
     for (void *b : bufs)
@@ -301,6 +308,9 @@ ph_status build_adjoint(ph_plan *p)
     };
     std::vector<Item> items;
     items.reserve((size_t)p->P);
+    std::vector<AdjRedRead> red;
+    int64_t grow = 0;  // per-pair gradient rows handed out so far
+    std::vector<char> has_pair(p->nr, 0);
     for (int32_t q = 0; q < p->nb; ++q) {
         const int32_t H = p->h_hb[q + 1] - p->h_hb[q];
         for (int32_t r = p->h_rb[q]; r < p->h_rb[q + 1]; ++r) {
@@ -311,17 +321,29 @@ ph_status build_adjoint(ph_plan *p)
                 p->adj_error = "adjoint supports reads up to 319 bases";
                 return p->adj_status;
             }
+            if (H > 0) has_pair[r] = 1;
+            // a read with several pairs: pair h's rows at grow + h m
+            if (H > 1) red.push_back(AdjRedRead{grow, p->h_ro[r], m, H});
             for (int32_t h = p->h_hb[q]; h < p->h_hb[q + 1]; ++h) {
                 Item it{};
                 it.r.read = r;
                 it.r.hap = h;
                 it.r.out = (int32_t)(p->h_out_off[q] + (int64_t)(r - p->h_rb[q]) * H + (h - p->h_hb[q]));
                 it.r.n = (int32_t)(p->h_ho[h + 1] - p->h_ho[h]);
+                it.r.direct = H == 1 ? 1 : 0;
+                it.r.grow = H == 1 ? 0 : grow + (int64_t)(h - p->h_hb[q]) * m;
                 it.P = P;
                 it.K = K;
                 items.push_back(it);
             }
+            if (H > 1) grow += (int64_t)H * m;
         }
+    }
+    for (int32_t r = 0; r < p->nr; ++r) p->adj_zero = p->adj_zero || !has_pair[r];
+    if (red.size() >= ((size_t)1 << 31)) {
+        p->adj_status = PH_ERR_UNSUPPORTED;
+        p->adj_error = "too many reads with several pairs";
+        return p->adj_status;
     }
     // configuration, then longest haplotype first
     std::sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
@@ -398,8 +420,15 @@ ph_status build_adjoint(ph_plan *p)
     if ((st = dalloc(&p->d_adj_ctr, (size_t)2 * kAdj64Classes + p->adj_runs.size()))) return p->adj_status = st;
     if ((st = dalloc(&p->d_q64, (size_t)kAdj64Classes * p->q64_stride))) return p->adj_status = st;
     if ((st = dalloc(&p->d_ws64, (size_t)p->grid64 * p->ws64_stride))) return p->adj_status = st;
+    if ((st = dalloc(&p->d_grad_pair, (size_t)std::max<int64_t>(grow, 1) * 7))) return p->adj_status = st;
+    if ((st = dalloc(&p->d_red, std::max<size_t>(red.size(), 1)))) return p->adj_status = st;
+    p->n_red = (int32_t)red.size();
     hipError_t e = hipMemcpy(p->d_adj_recs, recs.data(), recs.size() * sizeof(AdjRec), hipMemcpyHostToDevice);
     if (e != hipSuccess) return p->adj_status = fail(PH_ERR_HIP, "hipMemcpy: %s", hipGetErrorString(e));
+    if (!red.empty()) {
+        e = hipMemcpy(p->d_red, red.data(), red.size() * sizeof(AdjRedRead), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return p->adj_status = fail(PH_ERR_HIP, "hipMemcpy: %s", hipGetErrorString(e));
+    }
     return PH_OK;
 }
 
@@ -554,7 +583,9 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     }
     for (int c = 0; c < kRescueClasses; ++c)
         if (p->class_pairs[c])
-            p->rescue_grid[c] = (int)std::min<int64_t>(p->class_pairs[c], (int64_t)p->cus * fwd64_blocks_per_cu(c));
+            for (int v = 0; v < 2; ++v)
+                p->rescue_grid[v][c] =
+                    (int)std::min<int64_t>(p->class_pairs[c], (int64_t)p->cus * fwd64_blocks_per_cu(c, v == 0));
     p->plain_K = (max_m + 1 + 63) / 64;
     if (p->plain_K < 1) p->plain_K = 1;
     p->plain_grid = (int)std::min<int64_t>(std::max<int64_t>(P, 1), (int64_t)p->cus * plain32_blocks_per_cu(p->plain_K));
@@ -567,7 +598,8 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     if ((st = dalloc(&p->d_hist, kMaxKeys))) return st;
     if ((st = dalloc(&p->d_recs, std::max<int64_t>(P, 1)))) return st;
     if ((st = dalloc(&p->d_book, 1))) return st;
-    if ((st = dalloc(&p->d_rescue, (size_t)kRescueClasses * std::max<int64_t>(P, 1)))) return st;
+    if ((st = dalloc(&p->d_bad, 1))) return st;
+    if ((st = dalloc(&p->d_rescue, (size_t)kRescueQueues * std::max<int64_t>(P, 1)))) return st;
     if (p->long_pairs) {
         if ((st = dalloc(&p->d_bnd32, (size_t)(p->long_pairs * p->bnd_stride)))) return st;
         if ((st = dalloc(&p->d_bnd64, (size_t)(p->long_pairs * p->bnd_stride)))) return st;
@@ -726,7 +758,10 @@ ph_status enqueue_stage(ph_plan *p, int stage, const ph_problem *pb, const float
         }
     } else if (!p->opts.plain) {
         for (int c = 0; c < kRescueClasses; ++c)
-            if (p->rescue_grid[c]) HIPCHK(launch_fwd64(sa, c, p->rescue_grid[c], s));
+            if (p->rescue_grid[0][c]) HIPCHK(launch_fwd64(sa, c, true, p->rescue_grid[0][c], s));
+        // after every rescaled launch: the plain queues also hold what those passed on
+        for (int c = 0; c < kRescueClasses; ++c)
+            if (p->rescue_grid[1][c]) HIPCHK(launch_fwd64(sa, c, false, p->rescue_grid[1][c], s));
         if (p->long_pairs) {
             SweepArgs la = sa;
             la.bnd = p->d_bnd64;
@@ -751,14 +786,15 @@ void drop_graphs(ph_plan *p)
 }
 
 // The adjoint's launch sequence: parameter preparation, zeroing of the
-// gradient and of the counters (kernels, so that the sequence can be
-// captured), one persistent FP32 launch per (P, K) configuration, then the
-// FP64 launches of the classes present.
+// counters (and of the gradient when some read has no pair; kernels, so that
+// the sequence can be captured), one persistent FP32 launch per (P, K)
+// configuration, the FP64 launches of the classes present, then the
+// fixed-order sum of the per-pair rows of reads with several pairs.
 ph_status enqueue_backward(ph_plan *p, const ph_problem *pb, const float *log10_params,
                            const double *grad_log10L, float *grad_params, hipStream_t s)
 {
     if (log10_params) HIPCHK(launch_prep_params(log10_params, p->nread_bases, p->d_lin, s));
-    HIPCHK(launch_zero_f32(grad_params, p->nread_bases * 7, s));
+    if (p->adj_zero) HIPCHK(launch_zero_f32(grad_params, p->nread_bases * 7, s));
     HIPCHK(launch_zero_i32(p->d_adj_ctr, 2 * kAdj64Classes + (int)p->adj_runs.size(), s));
     AdjArgs a{};
     a.pb.read_offset = pb->read_offset;
@@ -773,6 +809,7 @@ ph_status enqueue_backward(ph_plan *p, const ph_problem *pb, const float *log10_
     a.ws = p->d_ws;
     a.grad_in = grad_log10L;
     a.grad_out = grad_params;
+    a.grad_pair = p->d_grad_pair;
     a.threshold = p->threshold;
     a.all_recs = p->d_adj_recs;
     a.q64 = p->d_q64;
@@ -798,6 +835,7 @@ ph_status enqueue_backward(ph_plan *p, const ph_problem *pb, const float *log10_
     // empty exits at once)
     for (int k = 1; k <= kAdj64Classes; ++k)
         if (p->class64[k - 1]) HIPCHK(launch_adj64(a, k, p->grid64, s));
+    HIPCHK(launch_adj_reduce(p->d_red, p->n_red, p->d_grad_pair, grad_params, s));
     return PH_OK;
 }
 
@@ -964,10 +1002,12 @@ ph_status ph_validate(ph_plan *p, const ph_problem *pb, void *stream_v)
     DevProblem d{};
     d.read_bases = pb->read_bases;
     d.hap_bases = pb->hap_bases;
-    HIPCHK(launch_reset_keys(p->d_hist, 0, p->d_book, s));
-    HIPCHK(launch_validate(d, p->nread_bases, p->nhap_bases, p->d_book, s));
+    // a counter of its own: the forward's bookkeeping (rescue counts, bin
+    // ranges) stays as the last forward call left it
+    HIPCHK(hipMemsetAsync(p->d_bad, 0, sizeof(int32_t), s));
+    HIPCHK(launch_validate(d, p->nread_bases, p->nhap_bases, p->d_bad, s));
     int32_t bad = 0;
-    HIPCHK(hipMemcpyAsync(&bad, &p->d_book->bad_code, sizeof(bad), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&bad, p->d_bad, sizeof(bad), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (bad) return fail(PH_ERR_INVALID, "%d base codes outside 0..4", bad);
     return PH_OK;
@@ -996,10 +1036,14 @@ ph_status ph_plan_rescued(ph_plan *p, int64_t *count)
     if (!p || !count) return fail(PH_ERR_INVALID, "NULL argument");
     if (!p->forward_done) return fail(PH_ERR_STATE, "no forward call recorded");
     HIPCHK(hipEventSynchronize(p->ev[3]));
-    int32_t c[kRescueClasses];
+    int32_t c[kRescueQueues], lc = 0, passed = 0;
     HIPCHK(hipMemcpy(c, p->d_book->rescue_count, sizeof(c), hipMemcpyDeviceToHost));
-    *count = 0;
-    for (int i = 0; i < kRescueClasses; ++i) *count += c[i];
+    HIPCHK(hipMemcpy(&lc, &p->d_book->long_rescue_count, sizeof(lc), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&passed, &p->d_book->rescue_passed, sizeof(passed), hipMemcpyDeviceToHost));
+    // pairs of reads longer than 1023 bases (windowed FP64 sweep), plus both
+    // sets of queues, less the pairs the rescaled sweep passed on (counted twice)
+    *count = lc - passed;
+    for (int i = 0; i < kRescueQueues; ++i) *count += c[i];
     return PH_OK;
 }
 

@@ -24,6 +24,11 @@ constexpr int kBuckets = 128;            // haplotype-length buckets per bin
 constexpr int kMaxKeys = kMaxBins * kBuckets;
 constexpr int kMaxReadLen = 1023;        // 64 lanes x 16 rows minus the absorbing row
 constexpr int kRescueClasses = 4;        // FP64 sweep: 64 lanes x {2, 4, 8, 16} rows
+// FP64 queues: [rescaled-state FP64 sweep | plain-state FP64 sweep] x class.
+// The FP32 sweep queues a pair that leaves the FP32 range into the first
+// set, one with a row outside the rescaled states into the second; the
+// rescaled FP64 sweep passes on what leaves its own range to the second.
+constexpr int kRescueQueues = 2 * kRescueClasses;
 // Longer reads run in windows of kLongRows rows (64 lanes x 16 rows): the
 // window's top boundary row comes from HBM, its bottom row goes back there
 constexpr int kLongRows = 1024;
@@ -54,9 +59,9 @@ struct Book {
     int32_t bin_tile_begin[kMaxBins + 1];  // tile range of every bin (persistent sweep)
     int32_t tile_counter;                  // plain sweep work cursor
     int32_t bin_counter[kMaxBins];         // FP32 sweep work cursor of every bin
-    int32_t rescue_count[kRescueClasses];  // FP64 queue lengths
-    int32_t rescue_counter[kRescueClasses];// FP64 sweep work cursors
-    int32_t bad_code;                      // validation: count of codes > 4
+    int32_t rescue_count[kRescueQueues];   // FP64 queue lengths
+    int32_t rescue_counter[kRescueQueues]; // FP64 sweep work cursors
+    int32_t rescue_passed;                 // pairs the rescaled FP64 sweep passed on
     int32_t long_counter[kMaxWindows];     // FP32 windowed passes: work cursor per window
     int32_t long64_counter[kMaxWindows];   // FP64 windowed passes: work cursor per window
     int32_t long_rescue_count;             // FP64 queue of long pairs
@@ -83,7 +88,7 @@ struct SweepArgs {
     Book *book;
     double *out_log10;
     uint8_t *out_status;
-    int32_t *rescue_list;        // [kRescueClasses][num_pairs]
+    int32_t *rescue_list;        // [kRescueQueues][rescue_stride]
     int64_t rescue_stride;       // = num_pairs
     double threshold;            // FP32: scaled-sum rescue threshold
     double floor64;              // FP64: scaled-sum floor
@@ -119,9 +124,23 @@ constexpr int kAdjR = PH_ADJ_R;  // FP32: recompute blocks per checkpoint
 constexpr int kAdjC64 = 2;  // FP64: forward steps per checkpoint block
 constexpr int kAdj64Classes = 5;  // FP64 adjoint: 64 lanes x 1..5 rows
 
+// A pair's gradient rows go to grad_out at its read's rows when the read has
+// no other pair (direct = 1), else to its own rows grow .. grow + m - 1 of
+// the per-pair array, which a fixed-order sum over the read's pairs reduces
+// into grad_out afterwards: every row is written by exactly one pair, so the
+// result does not depend on the order in which waves finish.
 struct AdjRec {
     int32_t read, hap, out, n;
-    int32_t S, pad;
+    int32_t S, direct;
+    int64_t grow;
+};
+
+// Reads whose gradient rows sum several pairs: pair h of the read holds
+// rows grow + h m .. grow + h m + m - 1 of the per-pair array.
+struct AdjRedRead {
+    int64_t grow;    // first per-pair row of the read's first pair
+    int64_t ro;      // the read's first base (row of grad_out)
+    int32_t m, H;
 };
 
 struct AdjArgs {
@@ -136,6 +155,7 @@ struct AdjArgs {
     int64_t ws_stride;
     const double *grad_in;  // per output pair
     float *grad_out;        // per read base x 7
+    float *grad_pair;       // per-pair rows x 7 (reads with several pairs)
     double threshold;       // FP32 scaled-sum range floor
     // FP64 pass over the pairs the FP32 pass left out
     const AdjRec *all_recs;
@@ -156,6 +176,8 @@ hipError_t launch_adj32(const AdjArgs &a, int P, int K, int grid, hipStream_t s)
 int adj32_blocks_per_cu(int P, int K);
 int adj64_blocks_per_cu(int K);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
+hipError_t launch_adj_reduce(const AdjRedRead *reads, int32_t nreads, const float *grad_pair, float *grad_out,
+                             hipStream_t s);
 hipError_t launch_zero_i32(int32_t *p, int n, hipStream_t s);
 int adj64_e_bytes(int K);
 hipError_t launch_adj64(const AdjArgs &a, int K, int grid, hipStream_t s);
@@ -171,17 +193,17 @@ hipError_t launch_plain32(const SweepArgs &a, int K, int grid, hipStream_t s);
 hipError_t launch_fwd32_single(const SweepArgs &a, int grid, hipStream_t s);
 int fwd32_single_blocks_per_cu();
 bool single_supported(int P, int K);
-hipError_t launch_fwd64(const SweepArgs &a, int cls, int grid, hipStream_t s);
+hipError_t launch_fwd64(const SweepArgs &a, int cls, bool rescaled, int grid, hipStream_t s);
 hipError_t launch_long32(const SweepArgs &a, int window, int grid, hipStream_t s);
 hipError_t launch_long64(const SweepArgs &a, int window, int grid, hipStream_t s);
 int long32_blocks_per_cu();
 int long64_blocks_per_cu();
 hipError_t launch_prep_params(const float *lg, int64_t npos, double *lin, hipStream_t s);
 hipError_t launch_validate(const DevProblem &pb, int64_t nread_bases, int64_t nhap_bases,
-                           Book *book, hipStream_t s);
+                           int32_t *bad, hipStream_t s);
 hipError_t launch_reset_keys(int32_t *hist, int nkeys, Book *book, hipStream_t s);
 int fwd32_blocks_per_cu(int P, int K);
-int fwd64_blocks_per_cu(int cls);
+int fwd64_blocks_per_cu(int cls, bool rescaled);
 int plain32_blocks_per_cu(int K);
 bool fwd32_supported(int P, int K);
 

@@ -250,7 +250,6 @@ __device__ __forceinline__ void cell_step_hat(T (&M)[K], T (&I)[K], T (&D)[K], T
                                               const T (&ke)[K], const T (&ep)[K], T eI, uint32_t keep,
                                               T eM = 0, T eD = 0)
 {
-    static_assert(sizeof(T) == 4, "rescaled states are an FP32 form");
     T Mu = shift_up<P>(M[K - 1]);
     T Iu = shift_up<P>(I[K - 1]);
     T Du = shift_up<P>(D[K - 1]);
@@ -385,8 +384,27 @@ __device__ __forceinline__ bool hat_row_unsafe(const DevProblem &pb, const doubl
                      c_pf[pb.gq[pos]], c_1mpf[pb.gq[pos]], fac, ci, cd, ke);
 }
 
+// Start scale of the rescaled states: FP32 2^120 (as the plain states); FP64
+// 2^1000, lower than the plain FP64 sweep's 2^1020 so that It and Dh, which
+// can exceed the largest M by a few binary orders, stay finite.
+template <typename T>
+struct RangeHat;
+template <>
+struct RangeHat<float> {
+    static constexpr int kExp = 120;
+};
+template <>
+struct RangeHat<double> {
+    static constexpr int kExp = 1000;
+};
+
 // Sweep one tile: up to G = 64/P pairs, one per lane group.  Group g takes
 // record rec_first + g (or rec_idx_list[rec_first + g]) if g < nvalid.
+//
+// H: rescaled states (M, It, Dh).  The FP32 sweeps always use them; the
+// FP64 sweep uses them for pairs that left the FP32 range (FP64 rescaled
+// sweep) and the plain states for pairs with a row outside the rescaled
+// states and for what the rescaled FP64 sweep passes on (plain FP64 sweep).
 //
 // Windowed mode (W, reads longer than kMaxReadLen; P = 64, one pair per
 // wave): the launch covers rows A.window * kLongRows + 1 .. + kLongRows of
@@ -395,14 +413,15 @@ __device__ __forceinline__ bool hat_row_unsafe(const DevProblem &pb, const doubl
 // at a time in LDS, and the window's last row is written back in place
 // (column j is read at step j-1 and written at step j+62).  Only the window
 // that holds the absorbing row m+1 produces the result.
-template <typename T, int P, int K, bool W = false, bool V = false>
+template <typename T, int P, int K, bool W = false, bool V = false, bool H = sizeof(T) == 4>
 __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int rec_first,
                            int nvalid, char *lds, int bnd_slot = 0)
 {
     using C = Cfg<T, P, K>;
     static_assert(!W || (P == 64 && K * P == kLongRows), "windowed sweep: 64 lanes x kLongRows / 64 rows");
-    // rescaled states (M, It, Dh) for the FP32 sweeps
-    constexpr bool HAT = sizeof(T) == 4;
+    static_assert(sizeof(T) == 4 || !H || (!W && !V), "FP64 rescaled states: the binned sum-product sweep only");
+    constexpr bool HAT = H;  // rescaled states (M, It, Dh)
+    constexpr int kExp = HAT ? RangeHat<T>::kExp : Range<T>::kExp;
     const int lane = threadIdx.x;
     const int g = lane / P;
     const int t = lane % P;
@@ -455,9 +474,9 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     T edge = 0;
     bool bad = false;  // rescaled states: one of my rows is outside what they carry
     bool phred32 = false;  // the FP32 sweep in Phred mode (rescaled states)
-    if constexpr (HAT) phred32 = lin == nullptr;
+    if constexpr (HAT && sizeof(T) == 4) phred32 = lin == nullptr;
     if (phred32) {
-      if constexpr (HAT) {
+      if constexpr (HAT && sizeof(T) == 4) {
         // FP32 sweep, Phred mode: all of the lane's loads issued at once,
         // decoded through the FP32 tables (1 - p and p/3 rounded from FP64);
         // the transition parameters first, then the E table with each real
@@ -499,7 +518,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             ke[r] = inner ? k : 0.0f;
             ep[r] = real ? e : (i == m ? 1.0f : 0.0f);
         }
-        if (t == 0 && m > 0 && r0 == 0) edge = ldexpf(c_1mpf[gq[0]], Range<T>::kExp) / (float)n;
+        if (t == 0 && m > 0 && r0 == 0) edge = ldexpf(c_1mpf[gq[0]], kExp) / (float)n;
 #pragma unroll
         for (int q = 0; q < C::NPL; ++q) {
             float lm[C::RPP], lx[C::RPP];
@@ -574,7 +593,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
                 zt[r] = *slot(4, r);
             }
         }
-        if (t == 0 && m > 0 && r0 == 0) edge = (T)(ldexp(load_beta(pb, lin, ro, c_prob), Range<T>::kExp) / (double)n);
+        if (t == 0 && m > 0 && r0 == 0) edge = (T)(ldexp(load_beta(pb, lin, ro, c_prob), kExp) / (double)n);
         // E[c][row] = lam of the row against haplotype code c (N matches all,
         // PAD = 0); rescaled states: times alpha on the read's rows after the first
 #pragma unroll 1
@@ -740,20 +759,36 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     // ---- epilogue: the lane that holds the row-m sum writes it ---------------
     const bool owner = HAT ? (rml >= 0 && rml < K) : (t == P - 1);
     if (gvalid && owner && fin) {
-        const double lg = log10(acc) - (double)Range<T>::kExp * 0.30102999566398119521;
-        A.out_log10[rec.out] = lg;
-        if (A.mode == kModeRescue) {
+        const double lg = log10(acc) - (double)kExp * 0.30102999566398119521;
+        const int cls = m < 128 ? 0 : m < 256 ? 1 : m < 512 ? 2 : 3;
+        if (A.mode == kModeRescue && sizeof(T) == 8 && HAT) {
+            // rescaled FP64 sweep: inside its range (and no row outside the
+            // rescaled states), or passed on to the plain FP64 sweep
+            if (!gbad && acc >= A.floor64 && acc <= 1.0e300) {
+                A.out_log10[rec.out] = lg;
+                if (A.out_status) A.out_status[rec.out] = 1;
+            } else {
+                const int q = kRescueClasses + cls;
+                const int slot = atomicAdd(&A.book->rescue_count[q], 1);
+                A.rescue_list[q * A.rescue_stride + slot] = ridx;
+                atomicAdd(&A.book->rescue_passed, 1);
+            }
+        } else if (A.mode == kModeRescue) {
+            A.out_log10[rec.out] = lg;
             if (A.out_status) A.out_status[rec.out] = (acc >= A.floor64) ? 1 : 2;
         } else {
+            A.out_log10[rec.out] = lg;
             const bool ok = !gbad && (acc >= A.threshold) && (acc <= 3.0e38);
             if (A.mode == kModeBinned && !ok) {
                 if (W) {
                     const int slot = atomicAdd(&A.book->long_rescue_count, 1);
                     A.long_rescue_list[slot] = ridx;
                 } else {
-                    const int cls = m < 128 ? 0 : m < 256 ? 1 : m < 512 ? 2 : 3;
-                    const int slot = atomicAdd(&A.book->rescue_count[cls], 1);
-                    A.rescue_list[cls * A.rescue_stride + slot] = ridx;
+                    // out of range: the rescaled FP64 sweep; a row outside the
+                    // rescaled states (or the max-product score): the plain one
+                    const int q = (gbad || V) ? kRescueClasses + cls : cls;
+                    const int slot = atomicAdd(&A.book->rescue_count[q], 1);
+                    A.rescue_list[q * A.rescue_stride + slot] = ridx;
                 }
                 if (A.out_status) A.out_status[rec.out] = 1;  // final value written by the FP64 sweep
             } else if (A.out_status) {
@@ -861,18 +896,20 @@ __global__ __launch_bounds__(64) void k_plain32(SweepArgs A)
     }
 }
 
-// FP64 sweep over one rescue queue (64 lanes per pair, K rows per lane).
-template <int K, bool V = false>
+// FP64 sweep over one rescue queue (64 lanes per pair, K rows per lane):
+// H = true, the rescaled states over the pairs that left the FP32 range;
+// H = false, the plain states over the second set of queues.
+template <int K, bool V = false, bool H = false>
 __global__ __launch_bounds__(64) void k_fwd64(SweepArgs A)
 {
     __shared__ __attribute__((aligned(16))) char lds[Cfg<double, 64, K>::LDS_BYTES];
-    const int cls = A.rescue_class;
-    const int count = A.book->rescue_count[cls];
-    const int32_t *list = A.rescue_list + cls * A.rescue_stride;
-    int tile = next_tile(&A.book->rescue_counter[cls]);
+    const int q = (H ? 0 : kRescueClasses) + A.rescue_class;
+    const int count = A.book->rescue_count[q];
+    const int32_t *list = A.rescue_list + q * A.rescue_stride;
+    int tile = next_tile(&A.book->rescue_counter[q]);
     while (tile < count) {
-        sweep_tile<double, 64, K, false, V>(A, list, tile, 1, lds);
-        tile = next_tile(&A.book->rescue_counter[cls]);
+        sweep_tile<double, 64, K, false, V, H>(A, list, tile, 1, lds);
+        tile = next_tile(&A.book->rescue_counter[q]);
     }
 }
 
@@ -1055,14 +1092,14 @@ __global__ __launch_bounds__(256) void k_prep_params(const float *lg, int64_t np
 }
 
 __global__ __launch_bounds__(256) void k_validate(const uint8_t *rb, int64_t nr, const uint8_t *hb,
-                                                  int64_t nh, Book *bk)
+                                                  int64_t nh, int32_t *bad_count)
 {
     int bad = 0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nr; i += (int64_t)gridDim.x * 256)
         bad += rb[i] > 4;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nh; i += (int64_t)gridDim.x * 256)
         bad += hb[i] > 4;
-    if (bad) atomicAdd(&bk->bad_code, bad);
+    if (bad) atomicAdd(bad_count, bad);
 }
 
 // ---------------------------------------------------------------------------
@@ -1152,17 +1189,20 @@ hipError_t launch_plain32(const SweepArgs &a_in, int K, int grid, hipStream_t s)
 
 static const int kRescueK[kRescueClasses] = {2, 4, 8, 16};
 
-hipError_t launch_fwd64(const SweepArgs &a, int cls, int grid, hipStream_t s)
+hipError_t launch_fwd64(const SweepArgs &a, int cls, bool rescaled, int grid, hipStream_t s)
 {
     SweepArgs b = a;
     b.rescue_class = cls;
     b.mode = kModeRescue;
-#define PH_L64(k)                                                                       \
-    case k:                                                                             \
-        if (b.viterbi)                                                                  \
-            hipLaunchKernelGGL((k_fwd64<k, true>), dim3(grid), dim3(64), 0, s, b);      \
-        else                                                                            \
-            hipLaunchKernelGGL((k_fwd64<k, false>), dim3(grid), dim3(64), 0, s, b);     \
+    if (b.viterbi && rescaled) return hipSuccess;  // the max-product score uses the plain queues only
+#define PH_L64(k)                                                                            \
+    case k:                                                                                  \
+        if (b.viterbi)                                                                       \
+            hipLaunchKernelGGL((k_fwd64<k, true, false>), dim3(grid), dim3(64), 0, s, b);    \
+        else if (rescaled)                                                                   \
+            hipLaunchKernelGGL((k_fwd64<k, false, true>), dim3(grid), dim3(64), 0, s, b);    \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_fwd64<k, false, false>), dim3(grid), dim3(64), 0, s, b);   \
         break;
     switch (kRescueK[cls]) {
         PH_L64(2) PH_L64(4) PH_L64(8) PH_L64(16)
@@ -1203,10 +1243,10 @@ hipError_t launch_prep_params(const float *lg, int64_t npos, double *lin, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_validate(const DevProblem &pb, int64_t nrb, int64_t nhb, Book *book, hipStream_t s)
+hipError_t launch_validate(const DevProblem &pb, int64_t nrb, int64_t nhb, int32_t *bad, hipStream_t s)
 {
     hipLaunchKernelGGL(k_validate, dim3(grid_for(nrb + nhb, 256 * 8, 4096)), dim3(256), 0, s,
-                       pb.read_bases, nrb, pb.hap_bases, nhb, book);
+                       pb.read_bases, nrb, pb.hap_bases, nhb, bad);
     return hipGetLastError();
 }
 
@@ -1239,13 +1279,13 @@ int plain32_blocks_per_cu(int K)
 int long32_blocks_per_cu() { return occupancy((const void *)k_long32<false>); }
 int long64_blocks_per_cu() { return occupancy((const void *)k_long64<false>); }
 
-int fwd64_blocks_per_cu(int cls)
+int fwd64_blocks_per_cu(int cls, bool rescaled)
 {
     switch (kRescueK[cls]) {
-    case 2: return occupancy((const void *)k_fwd64<2>);
-    case 4: return occupancy((const void *)k_fwd64<4>);
-    case 8: return occupancy((const void *)k_fwd64<8>);
-    case 16: return occupancy((const void *)k_fwd64<16>);
+    case 2: return occupancy(rescaled ? (const void *)k_fwd64<2, false, true> : (const void *)k_fwd64<2>);
+    case 4: return occupancy(rescaled ? (const void *)k_fwd64<4, false, true> : (const void *)k_fwd64<4>);
+    case 8: return occupancy(rescaled ? (const void *)k_fwd64<8, false, true> : (const void *)k_fwd64<8>);
+    case 16: return occupancy(rescaled ? (const void *)k_fwd64<16, false, true> : (const void *)k_fwd64<16>);
     }
     return 1;
 }

@@ -6,11 +6,13 @@ kept with the repository.
         stage and of every backward call's adjoint kernels
     python -m paper_2411_11547_amd.profsum counters DB [DB ...]
         per-dispatch PMC counter values of the library's kernels and copies
-    python -m paper_2411_11547_amd.profsum traffic FETCH_DB WRITE_DB COPY_MIB
+    python -m paper_2411_11547_amd.profsum traffic FETCH_DB WRITE_DB COPY_MIB [KERNEL]
         HBM bytes of one forward call's FP32 sweep kernels from a FETCH_SIZE
         run and a WRITE_SIZE run of the same command, each scaled by what the
         counter reads for a device copy of COPY_MIB MiB (bench.py
-        --copy-probe-mib) in the same run
+        --copy-probe-mib) in the same run; with KERNEL (a name prefix such as
+        k_adj32 or k_fwd64), the same scaled bytes per dispatch of every
+        kernel of that name instead
 
 Reads the databases only; runs nothing.
 """
@@ -133,6 +135,34 @@ def traffic(fetch_db, write_db, copy_mib):
     print(f"traffic_bytes_per_launch: {fetch_b + write_b:.6g}")
 
 
+def traffic_kernel(fetch_db, write_db, copy_mib, prefix):
+    copy_kib = float(copy_mib) * 1024.0
+    out = {}
+    for db, counter in ((fetch_db, "FETCH_SIZE"), (write_db, "WRITE_SIZE")):
+        copy = None
+        per = collections.OrderedDict()
+        for (disp, name), ctrs in _counters(db).items():
+            if counter not in ctrs:
+                continue
+            v, dur = ctrs[counter]
+            if prefix in name:
+                e = per.setdefault(name, [0, 0.0, 0.0])
+                e[0] += 1
+                e[1] += v
+                e[2] += dur
+            elif not name.startswith(("void ph::", "ph::")) and "copy" in name.lower():
+                copy = v if copy is None else max(copy, v)
+        scale = copy_kib / copy if copy else float("nan")
+        print(f"copy probe {copy_mib} MiB: {counter} read {copy:.6g} KiB (scale {scale:.4f})")
+        for name, (n, v, dur) in per.items():
+            out.setdefault(name, {})[counter] = (n, v * scale * 1024.0 / n, dur / n / 1e6)
+    for name, d in out.items():
+        f = d.get("FETCH_SIZE", (0, float("nan"), 0))
+        w = d.get("WRITE_SIZE", (0, float("nan"), 0))
+        print(f"{name}: {f[0]} dispatches; per dispatch fetch {f[1]:.6g} B + write {w[1]:.6g} B "
+              f"= {f[1] + w[1]:.6g} B, mean duration {f[2]:.4f} / {w[2]:.4f} ms")
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "kernels":
         kernels(argv[1])
@@ -140,6 +170,8 @@ def main(argv):
         counters(*argv[1:])
     elif len(argv) == 4 and argv[0] == "traffic":
         traffic(argv[1], argv[2], argv[3])
+    elif len(argv) == 5 and argv[0] == "traffic":
+        traffic_kernel(argv[1], argv[2], argv[3], argv[4])
     else:
         print(__doc__)
         return 2

@@ -50,6 +50,28 @@ def test_long_reads_against_oracle():
     check_against_oracle(prob, got, st, ref=ref)
 
 
+def test_rescued_count_includes_long_pairs():
+    """ph_plan_rescued counts every pair sent to an FP64 sweep, those of the
+    windowed long-read sweep included, and a ph_validate call after the
+    forward leaves that count as it was."""
+    import torch
+    prob = long_problem()
+    dev = binding.DeviceProblem(prob)
+    plan = binding.Plan(prob)
+    out, st = plan.forward(dev)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    r_idx, _ = prob.pair_index()
+    long_pair = prob.read_lengths[r_idx] > 1023
+    sent = st != binding.PAIR_FP32
+    say(f"  rescued {plan.rescued()}, FP64 statuses {int(sent.sum())} ({int((sent & long_pair).sum())} long)")
+    assert (sent & long_pair).sum() >= 2 and (sent & ~long_pair).sum() >= 1
+    assert plan.rescued() == int(sent.sum())
+    plan.validate(dev)
+    assert plan.rescued() == int(sent.sum())
+    plan.close()
+
+
 def test_long_reads_forced_fp64():
     prob = long_problem(seed=22)
     got, st = gpu_forward(prob, rescue_threshold=float("inf"))

@@ -315,6 +315,43 @@ def test_explicit_rows_outside_fp32_states():
         assert np.all(st[~flagged & inside] == binding.PAIR_FP32), st[~flagged & inside]
 
 
+def test_fp64_rescaled_and_plain_sweeps():
+    """The FP64 rescue runs in two sweeps: the rescaled states (It = I/delta,
+    Dh = D/zeta, start scale 2^1000) for pairs that left the FP32 range, then
+    the plain states for pairs with a row outside the rescaled states and for
+    what the rescaled sweep passes on (a sum outside its range).  Explicit
+    parameters whose delta falls by 10^-5.5 on each of twelve consecutive
+    rows (kE near 3e4, inside the rescaled states, but It growing by that
+    factor per row) and whose eps is near 1, every pair forced into FP64,
+    against the oracle; ph_plan_rescued counts every pair once."""
+    import torch
+    say("FP64 rescaled and plain sweeps")
+    prob = _ragged(46, [[40, 90, 150, 255, 300], [63, 120, 200]], [[80, 300, 700], [150, 260]])
+    par = oracle.params_from_phred(prob.base_qual, prob.ins_qual, prob.del_qual, prob.gcp_qual)
+    off = prob.read_offset
+    for r in (1, 3, 6):
+        a = off[r] + 20
+        par[a:a + 12, 2] = 10.0 ** (-1.0 - 5.5 * np.arange(1, 13))  # delta
+        par[a:a + 12, 3] = 0.999                                      # eps
+        par[a:a + 12, 1] = 1 - 0.999                                  # beta
+        par[a:a + 12, 0] = 1 - par[a:a + 12, 2] - par[a:a + 12, 4]    # alpha
+    lg = np.log10(par).astype(np.float32)
+    ref = oracle.forward(prob, log10_params=lg)
+    assert np.all(np.isfinite(ref))
+    dev = binding.DeviceProblem(prob)
+    x = torch.from_numpy(lg).cuda()
+    for kw in (dict(rescue_threshold=math.inf), dict()):
+        plan = binding.Plan(prob, **kw)
+        out, st = plan.forward(dev, x)
+        torch.cuda.synchronize()
+        got, st = out.cpu().numpy(), st.cpu().numpy()
+        check_against_oracle(prob, got, st, ref=ref, log10_params=lg)
+        assert plan.rescued() == int((st != binding.PAIR_FP32).sum()), (plan.rescued(), np.bincount(st))
+        if kw:
+            assert np.all(st != binding.PAIR_FP32)
+        plan.close()
+
+
 def test_fp64_floor_status():
     """Unrelated 500-1023 base reads against random haplotypes fall below the
     FP64 sweep's range (scaled sum < 2^-1000, log10 L below about -608):
@@ -367,8 +404,9 @@ def test_ungapped_closed_form_150x300(gap):
         top = max(logs)
         want = math.log10(p[0, 1] / n) + top + math.log10(sum(10 ** (x - top) for x in logs))
         if gap == 0.0:
-            assert abs(got[k] - want) <= TOL32, (k, got[k], want)
+            # every pair finishes in the FP64 sweep: held to the FP64 bound
             assert st[k] == binding.PAIR_FP64, (k, st[k])
+            assert abs(got[k] - want) <= TOL64, (k, got[k], want)
         elif r_idx[k] == h_idx[k]:
             assert want > -10.0
             assert abs(got[k] - want) <= TOL32, (k, got[k], want)

@@ -94,6 +94,38 @@ def test_closed_forms_random_params():
         assert 10 ** oracle.forward_pair(r2, h2, p) == pytest.approx(want, rel=1e-13)
 
 
+def closed_3x3(r, h, p):
+    """L of a 3 x 3 pair as the sum of its nine paths (written out in
+    tests/golden/hand_worked.txt), with per-row parameters p [3, 7] =
+    {alpha, beta, delta, eps, zeta, lam_match, lam_mismatch}: the deletion
+    path M(1,1)->D(1,2)->M(2,3)->I(3,3) uses zeta_1, beta_2 and delta_3, the
+    insertion path M(1,1)->I(2,1)->I(3,1) delta_2 and eps_3."""
+    al, be, de, ep, ze = (p[:, c] for c in range(5))
+    lam = lambda i, j: p[i - 1, 5] if (r[i - 1] == h[j - 1] or r[i - 1] == 4 or h[j - 1] == 4) else p[i - 1, 6]
+    tot = (lam(1, 1) * (al[1] * lam(2, 2) * (al[2] * lam(3, 3) + de[2])
+                        + de[1] * (be[2] * lam(3, 2) + ep[2])
+                        + ze[0] * be[1] * lam(2, 3) * de[2])
+           + lam(1, 2) * (al[1] * lam(2, 3) * de[2] + de[1] * (be[2] * lam(3, 3) + ep[2]))
+           + lam(1, 3) * de[1] * ep[2])
+    return be[0] / 3 * tot
+
+
+def test_closed_form_3x3_random_params():
+    rng = np.random.default_rng(17)
+    for trial in range(40):
+        p = random_params(rng, 3, normalised=bool(trial % 2))
+        r = rng.integers(0, 5, 3).astype(np.uint8)
+        h = rng.integers(0, 5, 3).astype(np.uint8)
+        want = closed_3x3(r, h, p)
+        assert 10 ** oracle.forward_pair(r, h, p) == pytest.approx(want, rel=1e-13)
+        assert bruteforce.likelihood(r, h, p)[0] == pytest.approx(want, rel=1e-13)
+
+
+@pytest.mark.parametrize("read,hap,expected", [c for c in _golden_cases() if len(c[0]) == 3 and len(c[1]) == 3])
+def test_golden_3x3_rows_follow_the_closed_form(read, hap, expected):
+    assert closed_3x3(codes(read), codes(hap), q20_params(3)) == pytest.approx(expected, rel=1e-14)
+
+
 def test_d00_reading_and_single_cell():
     # D(0,0) = 1/n: a 1x1 pair has the single path D(0,0) -> M(1,1)
     p = q20_params(1)
