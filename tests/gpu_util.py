@@ -61,3 +61,23 @@ def check_against_oracle(prob, got, status, ref=None, log10_params=None, pairs=N
     assert e32 <= TOL32, e32
     assert e64 <= TOL64, e64
     return err
+
+
+# FP32 sweep range: scaled sum 1e-28 at the start scale 2^120
+THRESHOLD_LOG10 = -28.0 - 120 * 0.30102999566398119521
+
+
+def check_plain_against_oracle(prob, got, status, ref=None):
+    """The plain single-bin kernel has no rescue: pairs inside the FP32 range
+    (status 0) are compared to TOL32; the others carry status 3, and the
+    oracle puts exactly those below the range threshold (within TOL32)."""
+    if ref is None:
+        ref = oracle.forward(prob)
+    s32 = status == binding.PAIR_FP32
+    s3 = status == binding.PAIR_FP32_UNRESCUED
+    assert np.all(s32 | s3), f"unexpected status values {np.unique(status)}"
+    assert np.all(ref[s3] < THRESHOLD_LOG10 + TOL32), "unrescued status on a pair inside the FP32 range"
+    assert np.all(ref[s32] > THRESHOLD_LOG10 - TOL32), "FP32 status on a pair below the FP32 range"
+    e32 = float(np.abs(got[s32] - ref[s32]).max()) if s32.any() else 0.0
+    say(f"  plain: pairs={len(ref)} fp32={int(s32.sum())} max|d|={e32:.3e} unrescued={int(s3.sum())}")
+    assert e32 <= TOL32, e32

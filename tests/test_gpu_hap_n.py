@@ -20,7 +20,8 @@ with those codes replaced by 4, which the oracle checks.
 import numpy as np
 import pytest
 
-from gpu_util import TOL32, binding, check_against_oracle, gpu_forward, oracle, say, wl
+from gpu_util import (TOL32, binding, check_against_oracle, check_plain_against_oracle, gpu_forward, oracle, say,
+                      wl)
 
 pytestmark = pytest.mark.gpu
 
@@ -111,9 +112,13 @@ def test_forward_hap_n_default_bins_single_and_plain():
     prob = hap_n_problem(80, [ms[::2], ms[1::2]], [[1, 64, 65, 129, 333], [3, 128, 250, 900]])
     ref = oracle.forward(prob)
     say(f"hap N, default bins: {prob.num_pairs} pairs")
-    for kw in (dict(), dict(use_graph=False), dict(plain=True, use_graph=False)):
+    for kw in (dict(), dict(use_graph=False)):
         got, st = gpu_forward(prob, **kw)
         check_against_oracle(prob, got, st, ref=ref)
+    # the plain kernel has no FP64 rescue: pairs below the FP32 range report status 3
+    got, st = gpu_forward(prob, plain=True, use_graph=False)
+    check_plain_against_oracle(prob, got, st, ref=ref)
+    assert (st == binding.PAIR_FP32).sum() >= 60
     short = hap_n_problem(81, [[1, 2, 20, 47, 48, 100, 255]], [[1, 64, 300]])
     got, st = gpu_forward(short, single_launch=True)
     check_against_oracle(short, got, st)
