@@ -155,6 +155,28 @@ ph_status ph_forward_batch(ph_plan *plan, const ph_problem *problem,
                            const float *log10_params, double *out_log10L,
                            uint8_t *out_status, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): the forward
+ * pass of ph_forward_batch without a plan.  It allocates nothing: its
+ * scratch (pair records, binning counters, FP64 queues, linear parameters)
+ * is one fixed array of 7.5 MB inside the library, one copy per GPU,
+ * held until the process ends.  Arguments as ph_forward_batch, with the
+ * shape (HOST arrays, read during the call) in place of the plan; the same
+ * values as a plan built with the library's own bin table (tune_table_path
+ * NULL, force_p 0) and the default rescue threshold.
+ * Limits: at most 65536 pairs, 16384 batches, reads of 1..1023 bases, and
+ * with log10_params at most 65536 read bases; larger problems give
+ * PH_ERR_UNSUPPORTED before any device work.  Counts that differ between
+ * shape and problem give PH_ERR_PLAN_MISMATCH.
+ * The first call on each device sets up that device (the array's address,
+ * constant tables) and must not itself be captured; later calls enqueue
+ * kernels only.  Every call on one GPU shares that GPU's array: calls whose
+ * work overlaps on the device (two streams, or two host threads) race, so
+ * order them on one stream or with events. */
+ph_status ph_forward_batch_noalloc(const ph_shape *shape, const ph_problem *problem,
+                                   const float *log10_params, double *out_log10L,
+                                   uint8_t *out_status, void *stream);
+
 /* Viterbi score (the max-product form of Eq. (1)-(3): every sum over
  * predecessor states a maximum, and the largest M(m,j) or I(m,j) instead of
  * their sum): out_log10V[P] receives log10 of the probability of each pair's

@@ -26,6 +26,7 @@ STATUS_NAMES = {0: "PH_OK", -1: "PH_ERR_INVALID", -2: "PH_ERR_UNSUPPORTED", -3: 
 PAIR_FP32, PAIR_FP64, PAIR_FP64_FLOOR, PAIR_FP32_UNRESCUED = 0, 1, 2, 3
 
 EXPORTS = ("ph_plan_opts_default", "ph_plan_create", "ph_plan_info", "ph_forward_batch", "ph_viterbi_batch",
+           "ph_forward_batch_noalloc",
            "ph_backward_batch", "ph_validate", "ph_plan_stage_ms", "ph_plan_rescued",
            "ph_plan_destroy", "ph_last_error", "ph_version",
            "ph_pipeline_opts_default", "ph_pipeline_create", "ph_pipeline_info", "ph_pipeline_forward",
@@ -83,6 +84,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.ph_forward_batch.argtypes = [P, ctypes.POINTER(PhProblem), P, P, P, P]
     lib.ph_viterbi_batch.argtypes = [P, ctypes.POINTER(PhProblem), P, P, P, P]
+    lib.ph_forward_batch_noalloc.argtypes = [ctypes.POINTER(PhShape), ctypes.POINTER(PhProblem), P, P, P, P]
     lib.ph_backward_batch.argtypes = [P, ctypes.POINTER(PhProblem), P, P, P, P]
     lib.ph_validate.argtypes = [P, ctypes.POINTER(PhProblem), P]
     lib.ph_plan_stage_ms.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
@@ -108,6 +110,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ph_host_free.argtypes = [P]
     lib.ph_host_free.restype = None
     for name in ("ph_plan_create", "ph_plan_info", "ph_forward_batch", "ph_viterbi_batch", "ph_backward_batch",
+                 "ph_forward_batch_noalloc",
                  "ph_validate", "ph_plan_stage_ms", "ph_plan_rescued", "ph_pipeline_create",
                  "ph_pipeline_info", "ph_pipeline_forward", "ph_pipeline_ms"):
         getattr(lib, name).restype = ctypes.c_int
@@ -195,6 +198,27 @@ def ph_forward_batch(plan, problem: PhProblem, log10_params, out_log10L, out_sta
 
 def ph_viterbi_batch(plan, problem: PhProblem, log10_params, out_log10V, out_status, stream):
     _check(load().ph_viterbi_batch(plan, ctypes.byref(problem), log10_params, out_log10V, out_status, stream))
+
+
+def ph_forward_batch_noalloc(shape: PhShape, problem: PhProblem, log10_params, out_log10L, out_status, stream):
+    _check(load().ph_forward_batch_noalloc(ctypes.byref(shape), ctypes.byref(problem), log10_params, out_log10L,
+                                           out_status, stream))
+
+
+def forward_noalloc(problem, dev, log10_params=None, out=None, status=None, stream=None):
+    """ph_forward_batch_noalloc on a `workloads.Problem` and its DeviceProblem:
+    (log10 L [P] float64, status [P] uint8) as device tensors."""
+    torch = _torch()
+    shape, keep = shape_of(problem)  # host shape arrays, read during the call
+    P = int(problem.num_pairs)
+    if out is None:
+        out = torch.empty(max(P, 1), dtype=torch.float64, device="cuda")
+    if status is None:
+        status = torch.empty(max(P, 1), dtype=torch.uint8, device="cuda")
+    lp = None if log10_params is None else ctypes.c_void_p(log10_params.data_ptr())
+    ph_forward_batch_noalloc(shape, dev.c, lp, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+                             stream or current_stream())
+    return out[:P], status[:P]
 
 
 def ph_backward_batch(plan, problem: PhProblem, log10_params, grad_log10L, grad_params, stream):

@@ -81,6 +81,18 @@ constexpr int64_t kAdjWs64Doubles = (int64_t)1 << 28;  // 2 GiB, FP64 pass
 
 int rescue_class_of(int m) { return m < 128 ? 0 : m < 256 ? 1 : m < 512 ? 2 : 3; }
 
+// The library's own bin table, shortest reads first: 16 lanes x K rows
+// (K = 1..16) up to 255 bases, then 64 lanes x K rows (K = 5..16).  Written
+// into a fixed array (the allocation-free forward uses it too); returns the
+// number of entries.
+int builtin_table(TuneEntry *t)
+{
+    int n = 0;
+    for (int K = 1; K <= 16; ++K) t[n++] = {16 * K - 1, 16, K};
+    for (int K = 5; K <= 16; ++K) t[n++] = {64 * K - 1, 64, K};
+    return n;
+}
+
 std::vector<TuneEntry> default_table(int force_p)
 {
     std::vector<TuneEntry> t;
@@ -90,8 +102,9 @@ std::vector<TuneEntry> default_table(int force_p)
                 t.push_back({force_p * K - 1, force_p, K});
         return t;
     }
-    for (int K = 1; K <= 16; ++K) t.push_back({16 * K - 1, 16, K});
-    for (int K = 5; K <= 16; ++K) t.push_back({64 * K - 1, 64, K});
+    TuneEntry b[kMaxBins];
+    const int nb = builtin_table(b);
+    t.assign(b, b + nb);
     return t;
 }
 
@@ -1044,6 +1057,237 @@ ph_status ph_plan_rescued(ph_plan *p, int64_t *count)
     // sets of queues, less the pairs the rescaled sweep passed on (counted twice)
     *count = lc - passed;
     for (int i = 0; i < kRescueQueues; ++i) *count += c[i];
+    return PH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free forward (ph_forward_batch_noalloc): the scratch of the
+// binning, the FP32 sweeps and the FP64 rescue lives in one fixed device
+// array of this library instead of plan-owned buffers.  Its layout, at
+// 256-byte aligned offsets: the bookkeeping (Book), the key histogram, the
+// read-length -> bin map, the pairs per tile of each bin, the batch output
+// offsets, the pair records, the FP64 queues and (explicit parameters) the
+// linear parameters of every read base.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kNaMaxPairs = (int64_t)1 << 16;
+constexpr int32_t kNaMaxBatches = 1 << 14;
+constexpr int64_t kNaMaxParamBases = (int64_t)1 << 16;  // explicit parameters: read bases
+constexpr size_t na_align(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kNaBook = 0;
+constexpr size_t kNaHist = na_align(kNaBook + sizeof(Book));
+constexpr size_t kNaM2bin = na_align(kNaHist + (size_t)kMaxKeys * sizeof(int32_t));
+constexpr size_t kNaBinG = na_align(kNaM2bin + (size_t)(kMaxReadLen + 2) * sizeof(int16_t));
+constexpr size_t kNaOutOff = na_align(kNaBinG + (size_t)kMaxBins * sizeof(int32_t));
+constexpr size_t kNaRecs = na_align(kNaOutOff + (size_t)(kNaMaxBatches + 1) * sizeof(int64_t));
+constexpr size_t kNaRescue = na_align(kNaRecs + (size_t)kNaMaxPairs * sizeof(PairRec));
+constexpr size_t kNaLin = na_align(kNaRescue + (size_t)kRescueQueues * kNaMaxPairs * sizeof(int32_t));
+constexpr size_t kNaBytes = na_align(kNaLin + (size_t)kNaMaxParamBases * 8 * sizeof(double));
+
+}  // namespace
+
+// One copy per GPU, held until the process ends.  In host code this name
+// is only a stand-in for the symbol: device addresses come from
+// hipGetSymbolAddress (NaDevice::base).
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+
+// Per-device state of the allocation-free forward, set up by the first call
+// on that device.
+struct NaDevice {
+    bool ready = false;
+    unsigned char *base = nullptr;  // device address of `scratch` on this device
+    int cus = 0;
+    int fwd32_cap[kMaxBins] = {};   // persistent grid cap of each built-in bin (bin order)
+    int fwd64_cap[2][kRescueClasses] = {};
+};
+
+std::mutex g_na_mu;
+NaDevice g_na[kNaMaxDevices];
+TuneEntry g_na_table[kMaxBins];  // the built-in table, shortest reads first
+int g_na_bins = 0;
+
+ph_status na_device_setup(int dev, NaDevice *&out)
+{
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    NaDevice &d = g_na[dev];
+    if (!d.ready) {
+        if (!g_na_bins) g_na_bins = builtin_table(g_na_table);
+        // the constant tables of the sweeps (per device) and the address of
+        // this device's copy of the scratch array
+        HIPCHK(upload_luts());
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        HIPCHK(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev));
+        for (int b = 0; b < g_na_bins; ++b) {
+            const TuneEntry &e = g_na_table[g_na_bins - 1 - b];
+            d.fwd32_cap[b] = d.cus * std::max(1, fwd32_blocks_per_cu(e.P, e.K));
+        }
+        for (int c = 0; c < kRescueClasses; ++c)
+            for (int v = 0; v < 2; ++v) d.fwd64_cap[v][c] = d.cus * std::max(1, fwd64_blocks_per_cu(c, v == 0));
+        d.base = (unsigned char *)ptr;
+        d.ready = true;
+    }
+    out = &d;
+    return PH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ph_status ph_forward_batch_noalloc(const ph_shape *shape, const ph_problem *pb, const float *log10_params,
+                                   double *out_log10L, uint8_t *out_status, void *stream_v)
+{
+    g_err.clear();
+    if (!shape || !pb) return fail(PH_ERR_INVALID, "shape or problem is NULL");
+    const int32_t nb = shape->num_batches, nr = shape->num_reads, nh = shape->num_haps;
+    if (nb < 0 || nr < 0 || nh < 0) return fail(PH_ERR_INVALID, "negative counts");
+    if (pb->num_batches != nb || pb->num_reads != nr || pb->num_haps != nh)
+        return fail(PH_ERR_PLAN_MISMATCH, "problem has %d batches, %d reads, %d haplotypes; shape has %d, %d, %d",
+                    pb->num_batches, pb->num_reads, pb->num_haps, nb, nr, nh);
+    if (nb > kNaMaxBatches)
+        return fail(PH_ERR_UNSUPPORTED, "%d batches exceed the allocation-free maximum of %d", nb, kNaMaxBatches);
+    if (nb > 0 && (!shape->batch_read_begin || !shape->batch_hap_begin))
+        return fail(PH_ERR_INVALID, "batch arrays are NULL");
+    if (!shape->read_offset || !shape->hap_offset) return fail(PH_ERR_INVALID, "offset arrays are NULL");
+    const int32_t *rb = shape->batch_read_begin, *hb = shape->batch_hap_begin;
+    const int64_t *ro = shape->read_offset, *ho = shape->hap_offset;
+    if (ro[0] != 0 || ho[0] != 0) return fail(PH_ERR_INVALID, "read_offset[0] and hap_offset[0] must be 0");
+    for (int32_t r = 0; r < nr; ++r) {
+        const int64_t m = ro[r + 1] - ro[r];
+        if (m < 1) return fail(PH_ERR_INVALID, "read %d has length %lld", r, (long long)m);
+        if (m > kMaxReadLen)
+            return fail(PH_ERR_UNSUPPORTED, "read %d has length %lld: the allocation-free forward takes reads up to %d",
+                        r, (long long)m, kMaxReadLen);
+    }
+    for (int32_t h = 0; h < nh; ++h) {
+        const int64_t n = ho[h + 1] - ho[h];
+        if (n < 1) return fail(PH_ERR_INVALID, "haplotype %d has length %lld", h, (long long)n);
+        if (n > (1 << 30)) return fail(PH_ERR_UNSUPPORTED, "haplotype %d is too long", h);
+    }
+    if (nb > 0 && (rb[0] != 0 || hb[0] != 0)) return fail(PH_ERR_INVALID, "batch ranges must start at 0");
+    int64_t P = 0;
+    for (int32_t q = 0; q < nb; ++q) {
+        if (rb[q + 1] < rb[q] || hb[q + 1] < hb[q] || rb[q + 1] > nr || hb[q + 1] > nh)
+            return fail(PH_ERR_INVALID, "batch %d has a bad read or haplotype range", q);
+        P += (int64_t)(rb[q + 1] - rb[q]) * (hb[q + 1] - hb[q]);
+    }
+    if (P > kNaMaxPairs)
+        return fail(PH_ERR_UNSUPPORTED, "%lld pairs exceed the allocation-free maximum of %lld", (long long)P,
+                    (long long)kNaMaxPairs);
+    const int64_t nbases = ro[nr];
+    if (log10_params && nbases > kNaMaxParamBases)
+        return fail(PH_ERR_UNSUPPORTED, "%lld read bases with explicit parameters exceed the allocation-free maximum of %lld",
+                    (long long)nbases, (long long)kNaMaxParamBases);
+    if (P == 0) return PH_OK;
+    if (!out_log10L) return fail(PH_ERR_INVALID, "out_log10L is NULL");
+    if (!pb->batch_read_begin || !pb->batch_hap_begin || !pb->read_offset || !pb->hap_offset ||
+        !pb->read_bases || !pb->hap_bases)
+        return fail(PH_ERR_INVALID, "problem has a NULL array");
+    if (!log10_params && (!pb->base_qual || !pb->ins_qual || !pb->del_qual || !pb->gcp_qual))
+        return fail(PH_ERR_INVALID, "Phred arrays are NULL and no log10 parameters were given");
+
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(PH_ERR_UNSUPPORTED, "device %d: too many devices", dev);
+    NaDevice *d = nullptr;
+    ph_status st = na_device_setup(dev, d);
+    if (st != PH_OK) return st;
+    const int nbins = g_na_bins;
+
+    // pairs per bin and per FP64 class, from the host shape
+    int64_t bin_pairs[kMaxBins] = {}, class_pairs[kRescueClasses] = {};
+    for (int32_t q = 0; q < nb; ++q) {
+        const int64_t H = hb[q + 1] - hb[q];
+        for (int32_t r = rb[q]; r < rb[q + 1]; ++r) {
+            const int m = (int)(ro[r + 1] - ro[r]);
+            int e = 0;
+            while (e < nbins - 1 && g_na_table[e].max_m < m) ++e;
+            bin_pairs[nbins - 1 - e] += H;
+            class_pairs[rescue_class_of(m)] += H;
+        }
+    }
+
+    unsigned char *base = d->base;
+    Book *book = (Book *)(base + kNaBook);
+    int32_t *hist = (int32_t *)(base + kNaHist);
+    int16_t *m2bin = (int16_t *)(base + kNaM2bin);
+    int32_t *binG = (int32_t *)(base + kNaBinG);
+    int64_t *out_off = (int64_t *)(base + kNaOutOff);
+    PairRec *recs = (PairRec *)(base + kNaRecs);
+    int32_t *rescue = (int32_t *)(base + kNaRescue);
+    double *lin = (double *)(base + kNaLin);
+    hipStream_t s = (hipStream_t)stream_v;
+
+    BinTable tab{};
+    tab.num_bins = nbins;
+    for (int e = 0; e < nbins; ++e) {
+        tab.max_m[e] = (int16_t)g_na_table[e].max_m;
+        tab.P[e] = (int8_t)g_na_table[e].P;
+    }
+    // binning (the set-up kernel writes what a plan uploads at creation;
+    // kernels only, so that a caller may capture the sequence)
+    if (log10_params) HIPCHK(launch_prep_params(log10_params, nbases, lin, s));
+    HIPCHK(launch_reset_keys(hist, nbins * kBuckets, book, s));
+    HIPCHK(launch_na_setup(pb->batch_read_begin, pb->batch_hap_begin, nb, out_off, m2bin, binG, tab, s));
+    BinArgs ba{};
+    ba.num_pairs = P;
+    ba.num_batches = nb;
+    ba.out_offset = out_off;
+    ba.batch_read_begin = pb->batch_read_begin;
+    ba.batch_hap_begin = pb->batch_hap_begin;
+    ba.read_offset = pb->read_offset;
+    ba.hap_offset = pb->hap_offset;
+    ba.m2bin = m2bin;
+    ba.num_bins = nbins;
+    ba.bin_G = binG;
+    ba.hist = hist;
+    ba.recs = recs;
+    ba.book = book;
+    HIPCHK(launch_bin_count(ba, s));
+    HIPCHK(launch_bin_scan(ba, s));
+    HIPCHK(launch_bin_scatter(ba, s));
+
+    // FP32 sweeps, longest bin first, then the FP64 rescue (all on `s`)
+    SweepArgs sa{};
+    sa.pb.read_offset = pb->read_offset;
+    sa.pb.read_bases = pb->read_bases;
+    sa.pb.bq = pb->base_qual;
+    sa.pb.iq = pb->ins_qual;
+    sa.pb.dq = pb->del_qual;
+    sa.pb.gq = pb->gcp_qual;
+    sa.pb.hap_offset = pb->hap_offset;
+    sa.pb.hap_bases = pb->hap_bases;
+    sa.lin_params = log10_params ? lin : nullptr;
+    sa.recs = recs;
+    sa.book = book;
+    sa.out_log10 = out_log10L;
+    sa.out_status = out_status;
+    sa.rescue_list = rescue;
+    sa.rescue_stride = P;
+    sa.threshold = 1e-28;
+    sa.floor64 = std::ldexp(1.0, -1000);
+    sa.num_bins = nbins;
+    for (int b = 0; b < nbins; ++b) sa.bins[b] = {g_na_table[nbins - 1 - b].P, g_na_table[nbins - 1 - b].K};
+    sa.plain_count = (int32_t)P;
+    sa.long_bin = -1;
+    for (int b = 0; b < nbins; ++b) {
+        if (!bin_pairs[b]) continue;
+        const int G = 64 / sa.bins[b].P;
+        const int grid = (int)std::min<int64_t>((bin_pairs[b] + G - 1) / G, d->fwd32_cap[b]);
+        HIPCHK(launch_fwd32(sa, sa.bins[b].P, sa.bins[b].K, b, grid, s));
+    }
+    for (int v = 0; v < 2; ++v)
+        for (int c = 0; c < kRescueClasses; ++c)
+            if (class_pairs[c])
+                HIPCHK(launch_fwd64(sa, c, v == 0, (int)std::min<int64_t>(class_pairs[c], d->fwd64_cap[v][c]), s));
     return PH_OK;
 }
 

@@ -52,6 +52,15 @@ struct BinCfg {
     int32_t P, K;        // lanes per pair, rows per lane
 };
 
+// A bin table by value (entries shortest reads first): entry e covers reads
+// up to max_m[e] bases with P[e] lanes per pair; bin b is entry
+// num_bins - 1 - b (bins are numbered longest first).
+struct BinTable {
+    int32_t num_bins;
+    int16_t max_m[kMaxBins];
+    int8_t P[kMaxBins];
+};
+
 // Device-side bookkeeping written by the binning kernels and read by the
 // sweeps; lives in one plan-owned buffer.
 struct Book {
@@ -202,6 +211,8 @@ hipError_t launch_prep_params(const float *lg, int64_t npos, double *lin, hipStr
 hipError_t launch_validate(const DevProblem &pb, int64_t nread_bases, int64_t nhap_bases,
                            int32_t *bad, hipStream_t s);
 hipError_t launch_reset_keys(int32_t *hist, int nkeys, Book *book, hipStream_t s);
+hipError_t launch_na_setup(const int32_t *rb, const int32_t *hb, int32_t nb, int64_t *out_offset,
+                           int16_t *m2bin, int32_t *bin_G, const BinTable &t, hipStream_t s);
 int fwd32_blocks_per_cu(int P, int K);
 int fwd64_blocks_per_cu(int cls, bool rescaled);
 int plain32_blocks_per_cu(int K);

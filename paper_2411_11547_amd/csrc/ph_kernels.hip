@@ -995,6 +995,42 @@ __global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
         if (h[i]) atomicAdd(&a.hist[i], h[i]);
 }
 
+// Set-up of the plan-free forward (ph_forward_batch_noalloc), one block:
+// the output offset of every batch (exclusive scan of |R_q| |H_q|), the
+// read-length -> bin map and the pairs per tile of every bin, which a plan
+// computes on the host and uploads once.
+__global__ __launch_bounds__(1024) void k_na_setup(const int32_t *rb, const int32_t *hb, int32_t nb,
+                                                   int64_t *out_offset, int16_t *m2bin, int32_t *bin_G,
+                                                   BinTable t)
+{
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    for (int m = tid; m <= kMaxReadLen + 1; m += 1024) {
+        int e = 0;
+        while (e < t.num_bins - 1 && t.max_m[e] < m) ++e;
+        m2bin[m] = (int16_t)(t.num_bins - 1 - e);
+    }
+    if (tid < t.num_bins) bin_G[tid] = 64 / t.P[t.num_bins - 1 - tid];
+    const int per = (nb + 1023) / 1024;
+    const int q0 = min(tid * per, nb), q1 = min(q0 + per, nb);
+    int64_t sum = 0;
+    for (int q = q0; q < q1; ++q) sum += (int64_t)(rb[q + 1] - rb[q]) * (hb[q + 1] - hb[q]);
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - sum;
+    for (int q = q0; q < q1; ++q) {
+        out_offset[q] = run;
+        run += (int64_t)(rb[q + 1] - rb[q]) * (hb[q + 1] - hb[q]);
+    }
+    if (tid == 1023) out_offset[nb] = part[1023];
+}
+
 // one block: exclusive scan of the key histogram (in place, becomes the
 // scatter cursors), record and tile ranges of every bin.
 __global__ __launch_bounds__(1024) void k_bin_scan(BinArgs a)
@@ -1233,6 +1269,13 @@ hipError_t launch_long64(const SweepArgs &a, int window, int grid, hipStream_t s
         hipLaunchKernelGGL(k_long64<true>, dim3(grid), dim3(64), 0, s, b);
     else
         hipLaunchKernelGGL(k_long64<false>, dim3(grid), dim3(64), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_na_setup(const int32_t *rb, const int32_t *hb, int32_t nb, int64_t *out_offset,
+                           int16_t *m2bin, int32_t *bin_G, const BinTable &t, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_na_setup, dim3(1), dim3(1024), 0, s, rb, hb, nb, out_offset, m2bin, bin_G, t);
     return hipGetLastError();
 }
 

@@ -128,3 +128,37 @@ def test_struct_layout_matches_binding(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def _noalloc_status(problem):
+    shape, keep = binding.shape_of(problem)
+    pb = binding.PhProblem(problem.num_batches, None, None, problem.num_reads, None, None, None, None, None,
+                           None, problem.num_haps, None, None)
+    st = binding.load().ph_forward_batch_noalloc(ctypes.byref(shape), ctypes.byref(pb), None, None, None, None)
+    return st, binding.load().ph_last_error().decode()
+
+
+def test_noalloc_rejects_sizes_beyond_its_maximum():
+    """The allocation-free forward refuses, before any device work, problems
+    larger than its fixed scratch: more than 65536 pairs, reads longer than
+    1023 bases, more than 16384 batches."""
+    many = wl.from_strings([(["ACGT"] * 257, ["ACGTT"] * 256)])  # 65792 pairs
+    st, msg = _noalloc_status(many)
+    assert st == -2 and "65536" in msg, msg
+    long = wl.from_strings([(["A" * 1024], ["ACGT"])])
+    st, msg = _noalloc_status(long)
+    assert st == -2 and "1023" in msg, msg
+    batches = wl.from_strings([(["A"], ["C"])] * 16385)
+    st, msg = _noalloc_status(batches)
+    assert st == -2 and "16384" in msg, msg
+    # empty read: invalid, as for a plan
+    bad = wl.from_strings([(["ACGT"], ["ACGTT"])])
+    bad.read_offset = np.array([0, 0], np.int64)
+    st, _ = _noalloc_status(bad)
+    assert st == -1
+    # counts that differ between shape and problem
+    ok = wl.from_strings([(["ACGT"], ["ACGTT"])])
+    shape, keep = binding.shape_of(ok)
+    pb = binding.PhProblem(1, None, None, 2, None, None, None, None, None, None, 1, None, None)
+    st = binding.load().ph_forward_batch_noalloc(ctypes.byref(shape), ctypes.byref(pb), None, None, None, None)
+    assert st == -5
