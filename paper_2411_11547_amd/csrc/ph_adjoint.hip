@@ -29,13 +29,19 @@
 // backward walks the blocks of CB steps in reverse: the wave reloads a
 // block's checkpoint, recomputes the block's CB steps as a wavefront (the
 // same lane exchange as the forward, so nothing else needs storing), keeps
-// them in registers and runs the reverse wavefront over them.
+// them in registers and runs the reverse wavefront over them.  In the FP32
+// pass the memory unit copies the next block's checkpoint into LDS while the
+// current block runs (global_load_lds), so the reload costs neither
+// registers nor a wait on memory.
 //
 // One persistent workgroup per slot takes a tile (G = 64/P pairs of one
 // (P, K) configuration), runs the checkpointed forward into its own slice of
 // the workspace and then the reverse sweep; the slice is read back soon after
 // it is written, in reverse order, and waves in the forward phase (stores)
-// overlap waves in the reverse phase (arithmetic).
+// overlap waves in the reverse phase (arithmetic).  Each pair writes its own
+// gradient rows (a read's rows directly when it has one pair, else rows of a
+// per-pair array that a fixed-order sum over the read's pairs reduces), so
+// no float atomics are needed and results do not depend on timing.
 //
 // Precision (the forward's FP32 sweep with FP64 recomputation, carried over
 // to the adjoint): an FP32 pass handles every pair; a pair whose scaled FP32
@@ -126,8 +132,9 @@ struct Pair2<double> {
 template <typename T, int P, int K>
 struct AdjCfg {
     static constexpr int G = 64 / P;
-    // E[code][row][lane] = (lam, w) with w = 1 for a mismatch, 0 otherwise
-    static constexpr int ENT = 2 * (int)sizeof(T);
+    // E[code][row][lane] = lam, negated where the row's base mismatches the
+    // code (the sign carries the mismatch flag; every lam is >= 0)
+    static constexpr int ENT = (int)sizeof(T);
     static constexpr int ROW_BYTES = 64 * ENT;
     static constexpr int CODE_BYTES = K * ROW_BYTES;
     static constexpr int E_BYTES = kCodes * CODE_BYTES;
@@ -135,8 +142,9 @@ struct AdjCfg {
 
 // Per-pair state shared by the forward and backward parts: the record, the
 // per-row coefficients of the lane's K rows (absorbing rows past the read end,
-// as in the forward sweep), the (lam, w) table and the haplotype staged in
-// LDS with PAD outside columns 1..n.
+// as in the forward sweep), the emission table with mismatches marked by the
+// sign, and the haplotype's codes staged in LDS with PAD outside columns
+// 1..n.
 //
 // FP32 (HAT): the forward's rescaled states Ih = beta_{i+1} I and
 // Dh = D / zeta_i, with al = alpha, cd = beta_i zeta_{i-1}, kd = beta_{i+1}
@@ -163,11 +171,13 @@ struct AdjPair {
     T al[K], be[K], de[K], ep[K], ze[K];  // plain states (be, de, ze unused with HAT)
     T cd[K], kd[K], ke[K];                // rescaled states
     char *E;
-    const char *El;      // the lane's column of the (lam, w) table
-    const uint16_t *hs;  // staged byte offsets of the table of each column's code; column j at hs[j + P]
+    const char *El;      // the lane's column of the emission table
+    const uint8_t *hs;   // staged haplotype codes (PAD outside 1..n); column j at hs[j + P]
+    T *ckl;              // FP32: the wave's LDS checkpoint buffer [3K+3][64], after the staged haplotypes
 
     // S: forward steps of the pair's group (a multiple of the checkpoint
-    // block); hs_bytes: LDS bytes per group for the staged haplotype.
+    // block); hs_bytes: LDS bytes per group for the staged haplotype (it
+    // follows the emission table).
     __device__ __forceinline__ void init(const AdjArgs &A, char *lds, const AdjRec &r_in, int S_in, int hs_bytes)
     {
         lane = threadIdx.x;
@@ -240,30 +250,27 @@ struct AdjPair {
 #pragma unroll
             for (int c = 0; c < kCodes; ++c) {
                 const bool match = code == (uint32_t)c || code == 4u || c == 4;
-                V2 v;
-                v.x = one ? (T)1 : (T)0;
-                v.y = (T)0;
-                if (real && c != kPad) {
-                    v.x = match ? (T)p.lm : (T)p.lx;
-                    v.y = match ? (T)0 : (T)1;
-                }
-                *(V2 *)(mine + c * C::CODE_BYTES + r * C::ROW_BYTES) = v;
+                T v = one ? (T)1 : (T)0;
+                if (real && c != kPad) v = match ? (T)p.lm : -(T)p.lx;
+                *(T *)(mine + c * C::CODE_BYTES + r * C::ROW_BYTES) = v;
             }
         }
-        uint16_t *h = (uint16_t *)(lds + C::E_BYTES + g * hs_bytes);
+        uint8_t *h = (uint8_t *)(lds + C::E_BYTES + g * hs_bytes);
         const uint8_t *hap = pb.hap_bases + pb.hap_offset[rec.hap];
         const int len = S + P + 2;
         for (int x = t; x < len; x += P) {
             const int j = x - P;
-            const uint32_t c = (j >= 1 && j <= n) ? clamp_code(hap[j - 1]) : (uint32_t)kPad;
-            h[x] = (uint16_t)(c * C::CODE_BYTES);
+            h[x] = (uint8_t)((j >= 1 && j <= n) ? clamp_code(hap[j - 1]) : (uint32_t)kPad);
         }
         hs = h;
         El = mine;
+        ckl = (T *)(lds + C::E_BYTES + C::G * hs_bytes);
         __syncthreads();
     }
 
-    __device__ __forceinline__ const char *ecol(int s) const { return El + hs[s - t + 1 + P]; }
+    // the code of the lane's column at step s, and that code's table column
+    __device__ __forceinline__ int hcode(int s) const { return hs[s - t + 1 + P]; }
+    __device__ __forceinline__ const char *ecol(int s) const { return El + hcode(s) * C::CODE_BYTES; }
 };
 
 // Lane t receives lane t-1's value.  With the rescaled states (FP32) a
@@ -294,11 +301,11 @@ __device__ __forceinline__ void adj_cell_step(const AdjPair<T, P, K> &pr, const 
     for (int r = 0; r < K; ++r) {
         T mr, ir, dr;
         if constexpr (AdjPair<T, P, K>::HAT) {
-            mr = lam[r] * fma(pr.al[r], md, fma(pr.cd[r], dd, id));
+            mr = fabs(lam[r]) * fma(pr.al[r], md, fma(pr.cd[r], dd, id));
             ir = fma(pr.ke[r], iu, pr.kd[r] * mu);
             dr = fma(pr.ep[r], do_[r], mo[r]);
         } else {
-            mr = lam[r] * fma(pr.al[r], md, fma(pr.be[r], id, dd));
+            mr = fabs(lam[r]) * fma(pr.al[r], md, fma(pr.be[r], id, dd));
             ir = fma(pr.ep[r], iu, pr.de[r] * mu);
             dr = fma(pr.ep[r], do_[r], pr.ze[r] * mo[r]);
         }
@@ -409,6 +416,56 @@ __device__ __forceinline__ void adj_load_ck(const T *ck, int q, int lane, T (&cq
     for (int v = 0; v < V; ++v) cq[v] = c0[v * 64];
 }
 
+// FP32: checkpoint q is copied from the workspace into the wave's LDS
+// buffer ckl ([V][64], the workspace's own layout) by the memory unit
+// (global_load_lds), so a block's checkpoint is in flight during the
+// previous block without holding registers.  Completion is tracked by vmcnt.
+template <int K>
+__device__ __forceinline__ void adj_stage_ck(const float *ck, int q, int lane, float *ckl)
+{
+    constexpr int V = AdjCk<float, K>::V;
+    const float *c0 = ck + (int64_t)q * V * 64 + lane;
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+        __builtin_amdgcn_global_load_lds((const void *)(c0 + v * 64),
+                                         (__attribute__((address_space(3))) void *)(ckl + v * 64), 4, 0, 0);
+}
+
+// s_waitcnt on gfx9: vmcnt(0) (every vector memory operation of the wave,
+// LDS copies included, has completed), lgkmcnt(0) (every LDS read has
+// returned); each also a compiler barrier for memory
+__device__ __forceinline__ void wait_vm0()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ void wait_lgkm0()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// v where the sign bit of s is NEG, else +0: an AND with the sign bit
+// spread over the word (exact)
+template <bool NEG>
+__device__ __forceinline__ float keep_if_sign(float v, float s)
+{
+    uint32_t mk = (uint32_t)(__builtin_bit_cast(int32_t, s) >> 31);
+    if constexpr (!NEG) mk = ~mk;
+    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) & mk);
+}
+
+template <bool NEG>
+__device__ __forceinline__ double keep_if_sign(double v, double s)
+{
+    uint64_t mk = (uint64_t)(__builtin_bit_cast(int64_t, s) >> 63);
+    if constexpr (!NEG) mk = ~mk;
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) & mk);
+}
+
 // Eight row sums of forward value x backward value, per row of the lane:
 // alpha, beta, mismatch emission, match emission, delta, eps (insert),
 // eps (delete), zeta.  The match and mismatch emission uses are summed
@@ -473,13 +530,28 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
     T bl_dn_prev = 0;
 
     const int NB = S / CB;  // fine blocks; the checkpoint of block b is b / R
-    // The checkpoint of the next block is prefetched into registers during
-    // the current one, except where those registers would spill.
-    constexpr bool PREFETCH = PH_ADJ_PREFETCH && (K < 5 || CB < 4 || sizeof(T) == 8);
+    // The checkpoint of the next block is fetched during the current one:
+    // FP32 into the wave's LDS buffer (no registers held), FP64 into registers.
+    constexpr bool LDSPF = sizeof(T) == 4;
+    constexpr bool PREFETCH = !LDSPF && PH_ADJ_PREFETCH;
     T cn[V];
+    if constexpr (LDSPF) {
+        wait_vm0();  // the forward's checkpoint stores have completed
+        adj_stage_ck<K>((const float *)ck, (NB - 1) / R, pr.lane, (float *)pr.ckl);
+    }
     if constexpr (PREFETCH) adj_load_ck<T, K>(ck, (NB - 1) / R, pr.lane, cn);
     for (int b = NB - 1; b >= 0; --b) {
-        if constexpr (!PREFETCH) adj_load_ck<T, K>(ck, b / R, pr.lane, cn);
+        if constexpr (LDSPF) {
+            wait_vm0();
+#pragma unroll
+            for (int v = 0; v < V; ++v) cn[v] = pr.ckl[v * 64 + pr.lane];
+            if (b > 0 && (b - 1) / R != b / R) {
+                wait_lgkm0();  // the reads above have the buffer's values before it is refilled
+                adj_stage_ck<K>((const float *)ck, (b - 1) / R, pr.lane, (float *)pr.ckl);
+            }
+        } else if constexpr (!PREFETCH) {
+            adj_load_ck<T, K>(ck, b / R, pr.lane, cn);
+        }
         const int q = b;  // steps of this block: q CB .. q CB + CB - 1
         // F[c]: lane state before step q CB + c; bb[c]: the values received
         // from the lane above at step q CB + c - 1 (bb[0]: from the checkpoint)
@@ -526,14 +598,11 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
         // reverse wavefront over the block
 #pragma unroll
         for (int c = CB - 1; c >= 0; --c) {
-            const char *e = pr.ecol(q * CB + c);
-            T lam[K], w[K];
+            const int code = pr.hcode(q * CB + c);
+            const char *e = pr.El + code * C::CODE_BYTES;
+            T lam[K];
 #pragma unroll
-            for (int r = 0; r < K; ++r) {
-                const V2 v = *(const V2 *)(e + r * C::ROW_BYTES);
-                lam[r] = v.x;
-                w[r] = v.y;
-            }
+            for (int r = 0; r < K; ++r) lam[r] = *(const T *)(e + r * C::ROW_BYTES);
             const T bi_dn = fma(keep, shift_down_raw<P>(BI[0]), edge_bi);
             const T bl_dn = keep * shift_down_raw<P>(BL[0]);  // Bl of the row below, next column
             T bid = bi_dn;            // B_I of the row below, this column
@@ -565,17 +634,20 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
                     bd = fma(pr.ep[r], BD[r], bld);  // B_D' = Bl below-right + eps B_D' right
                     bm = fma(an, bld, fma(dn, bid, pr.ze[r] * BD[r]));
                 }
-                const T bl = lam[r] * bm;
+                const T bl = fabs(lam[r]) * bm;
                 A.a[r] = fma(mdg, bl, A.a[r]);
                 if constexpr (HAT)
                     A.b[r] = fma(fma(pr.cd[r], ddg, idg), bl, A.b[r]);  // (Ih + cD Dh)_diag Bl
                 else
                     A.b[r] = fma(fma(pr.be[r], idg, ddg), bl, A.b[r]);  // (beta I + D')_diag Bl
-                // M(i,j) B_M(i,j) into the mismatch or the match sum (w is 0 or 1,
-                // so both factors are exact)
-                const T wf = w[r] * F[c + 1][0][r];
-                A.x[r] = fma(wf, bm, A.x[r]);
-                A.mt[r] = fma(F[c + 1][0][r] - wf, bm, A.mt[r]);
+                // M(i,j) B_M(i,j) into the mismatch or the match sum, by the row's
+                // mismatch bit for this column
+                const T mo = F[c + 1][0][r];
+                // M on a mismatch, else 0, and the other way round (bit masks:
+                // exact, and no subtraction that the compiler could fuse with
+                // the multiply that produced M)
+                A.x[r] = fma(keep_if_sign<true>(mo, lam[r]), bm, A.x[r]);
+                A.mt[r] = fma(keep_if_sign<false>(mo, lam[r]), bm, A.mt[r]);
                 A.d[r] = fma(mu, bi, A.d[r]);
                 A.ei[r] = fma(iu, bi, A.ei[r]);
                 A.ed[r] = fma(F[c][2][r], bd, A.ed[r]);
@@ -660,7 +732,7 @@ __device__ __forceinline__ void adj_emit_zero(const AdjArgs &A, const AdjPair<T,
 #define PH_ADJ_WAVES 2
 #endif
 template <int P, int K>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PH_ADJ_WAVES))) void k_adj32(AdjArgs A)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 3 ? 3 : PH_ADJ_WAVES))) void k_adj32(AdjArgs A)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     constexpr int G = 64 / P;
@@ -787,6 +859,8 @@ int adj_e_bytes(int P, int K)
 
 int adj64_e_bytes(int K) { return kCodes * K * AdjCfg<double, 64, 1>::ROW_BYTES; }
 
+int adj_ck_lds_bytes(int K) { return (3 * K + 3) * 64 * (int)sizeof(float); }
+
 static int occupancy(const void *fn, size_t lds)
 {
     int nb = 0;
@@ -796,7 +870,7 @@ static int occupancy(const void *fn, size_t lds)
 
 hipError_t launch_adj32(const AdjArgs &a, int P, int K, int grid, hipStream_t s)
 {
-    const size_t lds = (size_t)adj_e_bytes(P, K) + (size_t)(64 / P) * a.hs_bytes;
+    const size_t lds = (size_t)adj_e_bytes(P, K) + (size_t)(64 / P) * a.hs_bytes + (size_t)adj_ck_lds_bytes(K);
 #define PH_LA(p, k)                                                              \
     if (P == p && K == k) {                                                      \
         hipLaunchKernelGGL((k_adj32<p, k>), dim3(grid), dim3(64), lds, s, a);   \

@@ -389,8 +389,8 @@ ph_status build_adjoint(ph_plan *p)
             run.ntiles += 1;
             S_max = std::max(S_max, S);
         }
-        run.hs_bytes = ((2 * (S_max + P + 2) + 15) / 16) * 16;  // u16 per column
-        if ((int64_t)adj_e_bytes(P, K) + (int64_t)G * run.hs_bytes > 64 * 1024) {
+        run.hs_bytes = ((S_max + P + 2 + 15) / 16) * 16;  // one code byte per column
+        if ((int64_t)adj_e_bytes(P, K) + (int64_t)G * run.hs_bytes + adj_ck_lds_bytes(K) > 64 * 1024) {
             p->adj_status = PH_ERR_UNSUPPORTED;
             p->adj_error = "haplotype too long for the adjoint sweep";
             return p->adj_status;
@@ -416,7 +416,7 @@ ph_status build_adjoint(ph_plan *p)
         }
     }
     const int S64 = ((n_max + 63 + kAdjC64 - 1) / kAdjC64) * kAdjC64;
-    p->hs_bytes64 = ((2 * (S64 + 64 + 2) + 15) / 16) * 16;  // u16 per column
+    p->hs_bytes64 = ((S64 + 64 + 2 + 15) / 16) * 16;  // one code byte per column
     if ((int64_t)adj64_e_bytes(k64_max) + p->hs_bytes64 > 64 * 1024) {
         p->adj_status = PH_ERR_UNSUPPORTED;
         p->adj_error = "haplotype too long for the FP64 adjoint sweep";

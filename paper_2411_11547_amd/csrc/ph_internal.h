@@ -158,7 +158,7 @@ struct AdjArgs {
     const AdjRec *recs;     // records of one (P, K) configuration
     int64_t rec_base;       // index of recs[0] in all_recs
     int32_t nrec, ntiles;
-    int32_t hs_bytes;       // LDS bytes per group for the staged haplotype
+    int32_t hs_bytes;       // LDS bytes per group for the staged haplotype codes (one per column)
     int32_t *tile_next;     // work cursor of this launch
     float *ws;              // [grid][ws_stride] per-workgroup checkpoints
     int64_t ws_stride;
@@ -181,6 +181,7 @@ struct AdjArgs {
 hipError_t upload_luts_adjoint();
 bool adj_supported(int P, int K);
 int adj_e_bytes(int P, int K);
+int adj_ck_lds_bytes(int K);  // FP32 pass: LDS checkpoint buffer per workgroup
 hipError_t launch_adj32(const AdjArgs &a, int P, int K, int grid, hipStream_t s);
 int adj32_blocks_per_cu(int P, int K);
 int adj64_blocks_per_cu(int K);
