@@ -261,7 +261,7 @@ def cpu_baseline(prob, target_cells=2.0e10, seed=0):
     _, used = oracle.forward(prob, pairs=np.sort(take), return_threads=True)
     dt = time.perf_counter() - t0
     return {"value": round(sub_cells / dt / 1e9, 4), "unit": "GCUPS", "cores": int(used),
-            "kind": "oracle", "cpu_model": cpu_model(),
+            "kind": "oracle", "cpu_model": cpu_model(), "host_logical_cpus": os.cpu_count(),
             "sample": f"{len(take)} random pairs of the same batch ({sub_cells:.3e} cells, {dt:.1f} s), "
                       "FP64 full-matrix forward, gcc -O2"}
 

@@ -448,32 +448,18 @@ __device__ __forceinline__ void wait_lgkm0()
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// v where the sign bit of s is NEG, else +0: an AND with the sign bit
-// spread over the word (exact)
-template <bool NEG>
-__device__ __forceinline__ float keep_if_sign(float v, float s)
-{
-    uint32_t mk = (uint32_t)(__builtin_bit_cast(int32_t, s) >> 31);
-    if constexpr (!NEG) mk = ~mk;
-    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) & mk);
-}
-
-template <bool NEG>
-__device__ __forceinline__ double keep_if_sign(double v, double s)
-{
-    uint64_t mk = (uint64_t)(__builtin_bit_cast(int64_t, s) >> 63);
-    if constexpr (!NEG) mk = ~mk;
-    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) & mk);
-}
-
 // Eight row sums of forward value x backward value, per row of the lane:
-// alpha, beta, mismatch emission, match emission, delta, eps (insert),
-// eps (delete), zeta.  The match and mismatch emission uses are summed
-// separately (not the match uses as alpha + beta - mismatch uses, which
-// cancels on rows where nearly every probable alignment mismatches).
+// the alpha and the beta terms of M, each split into match columns (am, bm)
+// and mismatch columns (ax, bx, accumulated negative), delta, eps (insert),
+// eps (delete), zeta.  Every M(i,j) B_M(i,j) is its alpha term plus its beta
+// term, so the emission uses follow as sums of same-signed parts: match
+// alpha am + bm, mismatch -(alpha ax + bx); alpha and beta as
+// alpha (am - ax) and bm - bx.  No use count is a difference of two sums
+// (taking the match uses as alpha + beta - mismatch uses would cancel on
+// rows where nearly every probable alignment mismatches).
 template <typename T, int K>
 struct AdjSums {
-    T a[K], b[K], x[K], mt[K], d[K], ei[K], ed[K], z[K];
+    T am[K], ax[K], bm[K], bx[K], d[K], ei[K], ed[K], z[K];
 };
 
 // Reverse wavefront over the checkpointed forward of the wave's pairs.
@@ -525,7 +511,7 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
     for (int r = 0; r < K; ++r) {
         BI[r] = BL[r] = (T)0;
         BD[r] = (HAT && r == pr.rml) ? bscale : (T)0;
-        A.a[r] = A.b[r] = A.x[r] = A.mt[r] = A.d[r] = A.ei[r] = A.ed[r] = A.z[r] = (T)0;
+        A.am[r] = A.ax[r] = A.bm[r] = A.bx[r] = A.d[r] = A.ei[r] = A.ed[r] = A.z[r] = (T)0;
     }
     T bl_dn_prev = 0;
 
@@ -566,20 +552,24 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
         if (PREFETCH && b > 0) adj_load_ck<T, K>(ck, (b - 1) / R, pr.lane, cn);
 
         if constexpr (R > 1) {
-            // advance from the checkpoint at step (b / R) R CB to step q CB
+            // advance from the checkpoint at step (b / R) R CB to step q CB,
+            // CB steps at a time
 #pragma unroll 1
-            for (int s = (b / R) * R * CB; s < q * CB; ++s) {
-                T mu, iu, du;
-                adj_from_above<T, P, K>(pr, F[0][0], F[0][1], F[0][2], mu, iu, du);
-                T lam[K];
-                const char *e = pr.ecol(s);
+            for (int s0 = (b / R) * R * CB; s0 < q * CB; s0 += CB) {
 #pragma unroll
-                for (int r = 0; r < K; ++r) lam[r] = *(const T *)(e + r * C::ROW_BYTES);
-                adj_cell_step<T, P, K>(pr, F[0][0], F[0][1], F[0][2], F[0][0], F[0][1], F[0][2], mu, iu, bb[0][0],
-                                       bb[0][1], bb[0][2], lam);
-                bb[0][0] = mu;
-                bb[0][1] = iu;
-                bb[0][2] = du;
+                for (int c = 0; c < CB; ++c) {
+                    T mu, iu, du;
+                    adj_from_above<T, P, K>(pr, F[0][0], F[0][1], F[0][2], mu, iu, du);
+                    T lam[K];
+                    const char *e = pr.ecol(s0 + c);
+#pragma unroll
+                    for (int r = 0; r < K; ++r) lam[r] = *(const T *)(e + r * C::ROW_BYTES);
+                    adj_cell_step<T, P, K>(pr, F[0][0], F[0][1], F[0][2], F[0][0], F[0][1], F[0][2], mu, iu,
+                                           bb[0][0], bb[0][1], bb[0][2], lam);
+                    bb[0][0] = mu;
+                    bb[0][1] = iu;
+                    bb[0][2] = du;
+                }
             }
         }
 
@@ -609,7 +599,7 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
             T bl_below = bl_dn_prev;  // Bl of the row below, next column
 #pragma unroll
             for (int r = K - 1; r >= 0; --r) {
-                const T bld = bl_below;
+                const T bld = fabs(bl_below);  // BL carries the table entry's sign
                 // forward values around (i, j): row above at j and j-1, own row at j-1 and j
                 const T mu = (r == 0) ? bb[c + 1][0] : F[c + 1][0][r - 1];
                 const T iu = (r == 0) ? bb[c + 1][1] : F[c + 1][1][r - 1];
@@ -634,20 +624,19 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
                     bd = fma(pr.ep[r], BD[r], bld);  // B_D' = Bl below-right + eps B_D' right
                     bm = fma(an, bld, fma(dn, bid, pr.ze[r] * BD[r]));
                 }
-                const T bl = fabs(lam[r]) * bm;
-                A.a[r] = fma(mdg, bl, A.a[r]);
+                // Bl with the sign of the table entry: negative on a mismatch
+                // column; its match and mismatch parts (the other part is 0)
+                const T bl = lam[r] * bm;
+                const T blm = fmax(bl, (T)0), blx = fmin(bl, (T)0);
+                A.am[r] = fma(mdg, blm, A.am[r]);
+                A.ax[r] = fma(mdg, blx, A.ax[r]);
+                T y;  // the beta term's forward factor
                 if constexpr (HAT)
-                    A.b[r] = fma(fma(pr.cd[r], ddg, idg), bl, A.b[r]);  // (Ih + cD Dh)_diag Bl
+                    y = fma(pr.cd[r], ddg, idg);  // (Ih + cD Dh)_diag
                 else
-                    A.b[r] = fma(fma(pr.be[r], idg, ddg), bl, A.b[r]);  // (beta I + D')_diag Bl
-                // M(i,j) B_M(i,j) into the mismatch or the match sum, by the row's
-                // mismatch bit for this column
-                const T mo = F[c + 1][0][r];
-                // M on a mismatch, else 0, and the other way round (bit masks:
-                // exact, and no subtraction that the compiler could fuse with
-                // the multiply that produced M)
-                A.x[r] = fma(keep_if_sign<true>(mo, lam[r]), bm, A.x[r]);
-                A.mt[r] = fma(keep_if_sign<false>(mo, lam[r]), bm, A.mt[r]);
+                    y = fma(pr.be[r], idg, ddg);  // (beta I + D')_diag
+                A.bm[r] = fma(y, blm, A.bm[r]);
+                A.bx[r] = fma(y, blx, A.bx[r]);
                 A.d[r] = fma(mu, bi, A.d[r]);
                 A.ei[r] = fma(iu, bi, A.ei[r]);
                 A.ed[r] = fma(F[c][2][r], bd, A.ed[r]);
@@ -685,10 +674,12 @@ __device__ __forceinline__ void adj_emit(const AdjArgs &A, const AdjPair<T, P, K
     for (int r = 0; r < K; ++r) {
         const int i = pr.t * K + r;
         if (i >= pr.m) continue;
-        const double ga = (double)pr.al[r] * (double)s.a[r] * inv;
-        const double gb = (double)s.b[r] * inv;
-        const double gx = (double)s.x[r] * inv;
-        const double gm = (double)s.mt[r] * inv;
+        const double al = (double)pr.al[r];
+        const double am = (double)s.am[r], ax = (double)s.ax[r], bm = (double)s.bm[r], bx = (double)s.bx[r];
+        const double ga = al * (am - ax) * inv;    // ax <= 0, bx <= 0
+        const double gb = (bm - bx) * inv;
+        const double gx = -(al * ax + bx) * inv;  // mismatch emissions
+        const double gm = (al * am + bm) * inv;   // match emissions
         double gd, ge, gz;
         if constexpr (AdjPair<T, P, K>::HAT) {
             gd = (double)pr.kd[r] * (double)s.d[r] * inv;

@@ -23,7 +23,7 @@ import sqlite3
 import sys
 
 SWEEP = ("k_fwd32", "k_plain32", "k_long32")
-ADJ = ("k_adj32", "k_adj64")
+ADJ = ("k_adj32", "k_adj64", "k_adj_reduce")
 
 
 def _is_sweep(name):
@@ -67,9 +67,12 @@ def kernels(db):
     for name, (c, tot, gx, vg, ag, lds, scr) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
         print(f"{name[:52]:<52} {c:>5} {tot / 1e6:>10.3f} {tot / c / 1e6:>9.3f} {gx:>7} {vg:>5} {ag:>5} "
               f"{lds:>6} {scr:>7}")
-    for title, marker, members in (("FP32 sweep stage (forward and Viterbi calls)", "k_reset", SWEEP),
-                                   ("adjoint kernels", "k_zero_f32", ADJ)):
-        sp = _spans(rows, marker, members)
+    fwd = [r for r in rows if not any(k in r[0] for k in SWEEP) or _is_sweep(r[0])]
+    vit = [r for r in rows if not any(k in r[0] for k in SWEEP) or not _is_sweep(r[0])]
+    for title, rs, marker, members in (("FP32 sweep stage of the forward calls", fwd, "k_reset", SWEEP),
+                                       ("FP32 sweep stage of the Viterbi calls", vit, "k_reset", SWEEP),
+                                       ("adjoint kernels", rows, "k_zero_i32", ADJ)):
+        sp = [x for x in _spans(rs, marker, members) if x > 0]
         if not sp:
             continue
         print()

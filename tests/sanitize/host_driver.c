@@ -100,6 +100,26 @@ int main(void)
     if (st == PH_OK) ph_pipeline_destroy(pipe);
     ph_pipeline_destroy(NULL);
 
+    /* the allocation-free forward: shape checks before any device work; a
+     * good shape reaches the device set-up (HIP error without a GPU) */
+    ph_problem pb;
+    memset(&pb, 0, sizeof(pb));
+    pb.num_batches = 2;
+    pb.num_reads = 3;
+    pb.num_haps = 3;
+    expect("noalloc NULL shape", ph_forward_batch_noalloc(NULL, &pb, NULL, NULL, NULL, NULL), PH_ERR_INVALID);
+    sb = s;
+    sb.read_offset = ro_bad;
+    expect("noalloc empty read", ph_forward_batch_noalloc(&sb, &pb, NULL, NULL, NULL, NULL), PH_ERR_INVALID);
+    int64_t ro_1024[4] = {0, 10, 25, 25 + 1024};
+    sb = s;
+    sb.read_offset = ro_1024;
+    expect("noalloc read over 1023", ph_forward_batch_noalloc(&sb, &pb, NULL, NULL, NULL, NULL), PH_ERR_UNSUPPORTED);
+    ph_problem pm = pb;
+    pm.num_reads = 4;
+    expect("noalloc count mismatch", ph_forward_batch_noalloc(&s, &pm, NULL, NULL, NULL, NULL), PH_ERR_PLAN_MISMATCH);
+    expect("noalloc NULL output", ph_forward_batch_noalloc(&s, &pb, NULL, NULL, NULL, NULL), PH_ERR_INVALID);
+
     if (strstr(ph_version(), "gfx950") == NULL) {
         fprintf(stderr, "FAIL version %s\n", ph_version());
         ++failures;

@@ -281,3 +281,36 @@ def test_adjoint_gap_continuation_zero_rows():
     ref, _ = oracle_grad(prob, u)
     got, _ = gpu_grad(prob, u)
     compare(got, ref, "gcp 0 rows")
+
+
+def test_adjoint_small_emission_uses_relative():
+    """Rows where almost every probable alignment mismatches (a substituted
+    base at Q40) have match-emission uses down to about 1e-15, and rows that
+    match have mismatch uses that small: each of the two channels is summed
+    from same-signed terms, so it must hold to 1e-3 relative with an absolute
+    floor of 1e-14 (the general bound's 1e-6 floor would hide a cancellation
+    or a rounding residue of the other channel's magnitude)."""
+    say("adjoint, emission uses on substituted and matching rows, relative")
+    rng = np.random.default_rng(7)
+    hap = "".join(rng.choice(list("ACGT"), 300))
+    reads = []
+    for _ in range(16):
+        s0 = int(rng.integers(0, 150))
+        r = list(hap[s0:s0 + 150])
+        for p in rng.choice(150, 4, replace=False):
+            r[p] = rng.choice([c for c in "ACGT" if c != r[p]])
+        reads.append("".join(r))
+    prob = wl.from_strings([(reads, [hap])], base_q=40)
+    u = np.ones(prob.num_pairs)
+    ref, _ = oracle_grad(prob, u)
+    got, _ = gpu_grad(prob, u)
+    compare(got, ref, "substituted rows")
+    for ch, name in ((5, "match"), (6, "mismatch")):
+        r, g = ref[:, ch], got[:, ch]
+        small = r < 1e-4
+        err = np.abs(g - r)
+        bad = err > 1e-3 * np.abs(r) + 1e-14
+        say(f"  {name} uses: {int(small.sum())} rows below 1e-4 (smallest {r.min():.2e}), "
+            f"max rel err {float(np.max(err / (np.abs(r) + 1e-14))):.2e}")
+        assert small.sum() >= 50
+        assert not bad.any(), (name, np.argwhere(bad)[:5].ravel(), r[bad][:5], g[bad][:5])
