@@ -50,6 +50,40 @@ __device__ __forceinline__ double shift_up(double v)
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// The same shift for groups of 16, 32 or 64 lanes, with the group's first
+// lane keeping `old` instead of taking 0 (the DPP move leaves a lane whose
+// source lies outside the group unwritten).
+template <int P>
+__device__ __forceinline__ uint32_t shift_up_or(uint32_t old, uint32_t v)
+{
+    int x = (int)v, o = (int)old;
+    if constexpr (P == 16) {
+        x = __builtin_amdgcn_update_dpp(o, x, 0x111 /* row_shr:1 */, 0xf, 0xf, false);
+    } else if constexpr (P == 64) {
+        x = __builtin_amdgcn_update_dpp(o, x, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+    } else {
+        static_assert(P == 32, "lane groups of 16, 32 or 64");
+        int t = __builtin_amdgcn_update_dpp(o, x, 0x142 /* row_bcast:15 */, 0xa, 0x1, false);
+        x = __builtin_amdgcn_update_dpp(t, x, 0x111 /* row_shr:1 */, 0xf, 0xf, false);
+    }
+    return (uint32_t)x;
+}
+
+template <int P>
+__device__ __forceinline__ float shift_up_or(float old, float v)
+{
+    return __builtin_bit_cast(float, shift_up_or<P>(__builtin_bit_cast(uint32_t, old), __builtin_bit_cast(uint32_t, v)));
+}
+
+template <int P>
+__device__ __forceinline__ double shift_up_or(double old, double v)
+{
+    const uint64_t o = __builtin_bit_cast(uint64_t, old), u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = shift_up_or<P>((uint32_t)o, (uint32_t)u);
+    const uint32_t hi = shift_up_or<P>((uint32_t)(o >> 32), (uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 template <typename T>
 struct Range;
 template <>

@@ -292,6 +292,88 @@ __device__ __forceinline__ void cell_step_hat(T (&M)[K], T (&I)[K], T (&D)[K], T
     Dd = Du;
 }
 
+// cell_step_hat with the first row's sums formed by the lane above: at the
+// start of a step every lane forms, from its last row's (M, It, Dh) at its
+// column, the two sums the next lane's first row needs,
+//   X = M + cD' Dh + cI' It  and  Y = M + kE' It
+// with the next lane's first-row coefficients (cib, cdb, keb), and hands on
+// X and Y instead of the three states: two lane shifts per step instead of
+// three (four DPP moves instead of six in FP64).  The receiving row then
+// costs M = lam X (X of the step before, held in Xd), It = Y and the Dh
+// update; the sums are the same operations in the same order as in
+// cell_step_hat, so the results are bit-identical.  In the first lane of a
+// group X is the row-0 boundary value eX (the It edge, cI = 1 on the read's
+// first row; Xd starts at eX) and Y is 0 (kE = 0 there).  Not used by the
+// windowed sweep, whose first lane takes a stored row.
+template <typename T, int P, int K, bool V = false>
+__device__ __forceinline__ void cell_step_hx(T (&M)[K], T (&I)[K], T (&D)[K], T &Xd, const T *lam,
+                                             const T (&ci)[K], const T (&cd)[K], const T (&ke)[K],
+                                             const T (&ep)[K], T cib, T cdb, T keb, T eX, uint32_t keep)
+{
+    T X, Y;
+    if constexpr (V) {
+        X = max_nonneg(max_nonneg(M[K - 1], cib * I[K - 1]), cdb * D[K - 1]);
+        Y = max_nonneg(M[K - 1], keb * I[K - 1]);
+    } else {
+        X = fma(cib, I[K - 1], fma(cdb, D[K - 1], M[K - 1]));
+        Y = fma(keb, I[K - 1], M[K - 1]);
+    }
+    T Yu = shift_up<P>(Y);
+    if constexpr (P < 16) Yu = __builtin_bit_cast(T, __builtin_bit_cast(uint32_t, Yu) & keep);
+    T mdg = M[0], idg = I[0], ddg = D[0];
+    M[0] = lam[0] * Xd;
+    if constexpr (P < 16) {
+        Xd = __builtin_bit_cast(T, __builtin_bit_cast(uint32_t, shift_up<P>(X)) & keep) + eX;
+    } else {
+        // the first lane keeps its X, which is eX at every step
+        Xd = shift_up_or<P>(Xd, X);
+    }
+    I[0] = Yu;
+    if constexpr (V)
+        D[0] = max_nonneg(mdg, ep[0] * ddg);
+    else
+        D[0] = fma(ep[0], ddg, mdg);
+    T mup = M[0], iup = I[0];
+#pragma unroll
+    for (int r = 1; r < K; ++r) {
+        const T mo = M[r], io = I[r], dol = D[r];
+        T mn, in, dn;
+        if constexpr (V) {
+            mn = lam[r] * max_nonneg(max_nonneg(mdg, ci[r] * idg), cd[r] * ddg);
+            in = max_nonneg(mup, ke[r] * iup);
+            dn = max_nonneg(mo, ep[r] * dol);
+        } else {
+            T x = fma(cd[r], ddg, mdg);
+            x = fma(ci[r], idg, x);
+            mn = lam[r] * x;
+            in = fma(ke[r], iup, mup);
+            dn = fma(ep[r], dol, mo);
+        }
+        M[r] = mn;
+        I[r] = in;
+        D[r] = dn;
+        mdg = mo;
+        idg = io;
+        ddg = dol;
+        mup = mn;
+        iup = in;
+    }
+}
+
+// lane t receives lane t+1's value over the whole wave (lane 63: 0)
+__device__ __forceinline__ float from_next_lane(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130 /* wave_shl:1 */,
+                                                              0xf, 0xf, true));
+}
+__device__ __forceinline__ double from_next_lane(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x130, 0xf, 0xf, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0x130, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // One step of the windowed sweep (64 lanes): lane 0 takes the staged
 // boundary values of its column, and the last lane writes the window's last
 // row at its column back to the boundary slot unless this is the final window.
@@ -664,6 +746,14 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     // row above the lane's first row at column j-1 = 0: the first lane's
     // row-0 boundary (the edge value) sits in It (rescaled) or Dt (plain)
     T Md = 0, Id = HAT ? edge : (T)0, Dd = HAT ? (T)0 : edge;
+    // rescaled states outside the windowed sweep (cell_step_hx): the first
+    // row's X at column 0, and the next lane's first-row coefficients
+    T Xd = edge, cib = 0, cdb = 0, keb = 0;
+    if constexpr (HAT && !W) {
+        cib = from_next_lane(ci[0]);
+        cdb = from_next_lane(cd[0]);
+        keb = from_next_lane(ke[0]);
+    }
     // row-m sum (Viterbi: maximum).  Plain states: each 64-step chunk in T,
     // then FP64.  Rescaled states: the absorbing row's Dh, flushed into FP64
     // every 64 steps by the lane that holds it (row index rml).
@@ -714,9 +804,9 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
                     window_step_hat<T, K, V>(M, I, D, Md, Id, Dd, lb, ci, cd, ke, ep, edge, top, u + 1, t, fin,
                                              bnd, s0 + u + 1, n);
                 } else {
-                    cell_step_hat<T, P, K, false, V>(M, I, D, Md, Id, Dd, la, ci, cd, ke, ep, edge, keep);
+                    cell_step_hx<T, P, K, V>(M, I, D, Xd, la, ci, cd, ke, ep, cib, cdb, keb, edge, keep);
                     load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
-                    cell_step_hat<T, P, K, false, V>(M, I, D, Md, Id, Dd, lb, ci, cd, ke, ep, edge, keep);
+                    cell_step_hx<T, P, K, V>(M, I, D, Xd, lb, ci, cd, ke, ep, cib, cdb, keb, edge, keep);
                 }
             }
             // the absorbing row's Dh (Viterbi: its running maximum) moves
