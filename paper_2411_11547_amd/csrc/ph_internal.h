@@ -13,11 +13,14 @@ namespace ph {
 constexpr int kCodes = 6;
 constexpr int kPad = 5;
 
-// Haplotype ring buffer per lane group in LDS: 4 chunks of 64 columns plus a
-// 64-byte mirror of chunk 0, so a block of 64 consecutive steps never wraps.
-constexpr int kChunk = 64;
-constexpr int kRing = 256;
-constexpr int kRingAlloc = 320;
+// Haplotype ring buffer per lane group in LDS: 4 chunks of ring_chunk(P)
+// columns plus a mirror of chunk 0, so the reads of a block of that many
+// consecutive steps never wrap.  Groups of up to 32 lanes use chunks of 32
+// columns: a ring of 320 bytes per group, which gives the configurations
+// whose LDS sets their occupancy (16 lanes x 11-14 rows) one more wave per
+// CU than chunks of 64; one 64-lane group per wave keeps chunks of 64.
+constexpr int ring_chunk(int P) { return P == 64 ? 64 : 32; }
+constexpr int ring_alloc(int P) { return 5 * ring_chunk(P); }
 
 constexpr int kMaxBins = 48;             // length bins (tuned table + the long-read bin)
 constexpr int kBuckets = 128;            // haplotype-length buckets per bin

@@ -44,10 +44,10 @@
 //    m is.  Rescaled states: row m+1 has lam = 1, cD = 0 and cI = delta_m,
 //    so M(m+1,j) = M(m,j-1) + I(m,j-1), and its Dh (eps = 1) sums that along
 //    the row (max-product: keeps its running maximum): the row-(m+1) lane
-//    flushes it into an FP64 accumulator every 64 steps.  Later rows have
-//    every coefficient 0: their M and Dh are exactly zero, and so is It from
-//    row m+3 on.  (The paper pads reads with
-//    N, which would change L if read at row pK.)
+//    flushes it into an FP64 accumulator every chunk of the haplotype ring
+//    (32 or 64 steps).  Later rows have every coefficient 0: their M and Dh
+//    are exactly zero, and so is It from row m+3 on.  (The paper pads reads
+//    with N, which would change L if read at row pK.)
 //  * Columns past the haplotype end carry a PAD code whose emission is 0, so
 //    groups of one wave may have different n and still add only exact zeros.
 //  * D(0, j) = 1/n is scaled by 2^120 (FP32) or 2^1020 (FP64) so that the
@@ -97,7 +97,7 @@ struct Cfg {
     static constexpr int KP = NPL * RPP;
     static constexpr int CODE_BYTES = NPL * 512;
     static constexpr int E_BYTES = kCodes * CODE_BYTES;
-    static constexpr int RING_BYTES = kRingAlloc * 2;  // u16 E-table offsets
+    static constexpr int RING_BYTES = ring_alloc(P) * 2;  // u16 E-table offsets
     static constexpr int LDS_BYTES = E_BYTES + G * RING_BYTES;
 };
 
@@ -117,38 +117,47 @@ __device__ __forceinline__ void load_lam(T *lam, const char *ebase)
     }
 }
 
-// Chunk `chunk` (64 columns) of the group's haplotype goes into its ring as
-// byte offsets of the code's E table (code * code_bytes), in two parts so
+// Chunk `chunk` (ring_chunk(P) columns) of the group's haplotype goes into its ring
+// as byte offsets of the code's E table (code * code_bytes), in two parts so
 // that the global-load latency overlaps a chunk of the sweep: ring_load
 // issues lane t's loads into registers (0xffff marks a column past the
 // haplotype end; nothing waits on the loads here), ring_store converts and
 // writes them.  Chunk c + 2 is loaded at the start of the sweep's chunk c and
 // written at its end, into the slot of chunk c - 2, which no lane reads after
-// the sweep's chunk c.
+// the sweep's chunk c (lane 63 of a 64-lane group, the furthest behind,
+// reads chunk c - 1 during chunk c).  Each lane takes ring_chunk(P) / P
+// columns.
 template <int P>
-__device__ __forceinline__ void ring_load(uint32_t (&c)[kChunk / P], int chunk, const uint8_t *hap, int n, int t)
+struct RingPer {
+    static constexpr int CH = ring_chunk(P);
+    static constexpr int N = CH / P;
+    static_assert(N >= 1, "a chunk has at least one column per lane");
+};
+
+template <int P>
+__device__ __forceinline__ void ring_load(uint32_t (&c)[RingPer<P>::N], int chunk, const uint8_t *hap, int n, int t)
 {
-    constexpr int PER = kChunk / P;
+    constexpr int PER = RingPer<P>::N;
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
-        const int col = chunk * kChunk + t * PER + b;
+        const int col = chunk * RingPer<P>::CH + t * PER + b;
         c[b] = col < n ? (uint32_t)hap[col] : 0xffffu;
     }
 }
 
 template <int P>
-__device__ __forceinline__ void ring_store(uint16_t *ring, int chunk, const uint32_t (&c)[kChunk / P], int t,
+__device__ __forceinline__ void ring_store(uint16_t *ring, int chunk, const uint32_t (&c)[RingPer<P>::N], int t,
                                            int code_bytes)
 {
-    constexpr int PER = kChunk / P;
+    constexpr int PER = RingPer<P>::N, CH = RingPer<P>::CH;
     const int slot = chunk & 3;
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
         const int x = t * PER + b;
         const uint32_t code = c[b] == 0xffffu ? (uint32_t)kPad : clamp_code(c[b]);
         const uint16_t off = (uint16_t)(code * code_bytes);
-        ring[slot * kChunk + x] = off;
-        if (slot == 0) ring[kRing + x] = off;
+        ring[slot * CH + x] = off;
+        if (slot == 0) ring[4 * CH + x] = off;
     }
 }
 
@@ -491,7 +500,7 @@ struct RangeHat<double> {
 // Windowed mode (W, reads longer than kMaxReadLen; P = 64, one pair per
 // wave): the launch covers rows A.window * kLongRows + 1 .. + kLongRows of
 // the pair.  Its top boundary row (the states of the row above, columns
-// 0..n) is read from the pair's slot `bnd_slot` of A.bnd, staged 64 columns
+// 0..n) is read from the pair's slot `bnd_slot` of A.bnd, staged a chunk
 // at a time in LDS, and the window's last row is written back in place
 // (column j is read at step j-1 and written at step j+62).  Only the window
 // that holds the absorbing row m+1 produces the result.
@@ -728,10 +737,10 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
         gbad = (bm & gm) != 0;
     }
     // haplotype ring: PAD everywhere (negative columns read slot 3), then chunks 0 and 1
-    for (int x = t; x < kRingAlloc; x += P) ring[x] = (uint16_t)(kPad * C::CODE_BYTES);
+    for (int x = t; x < ring_alloc(P); x += P) ring[x] = (uint16_t)(kPad * C::CODE_BYTES);
     __syncthreads();
     {
-        uint32_t c0[kChunk / P], c1[kChunk / P];
+        uint32_t c0[RingPer<P>::N], c1[RingPer<P>::N];
         ring_load<P>(c0, 0, hap, n, t);
         ring_load<P>(c1, 1, hap, n, t);
         ring_store<P>(ring, 0, c0, t, C::CODE_BYTES);
@@ -754,9 +763,10 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
         cdb = from_next_lane(cd[0]);
         keb = from_next_lane(ke[0]);
     }
-    // row-m sum (Viterbi: maximum).  Plain states: each 64-step chunk in T,
-    // then FP64.  Rescaled states: the absorbing row's Dh, flushed into FP64
-    // every 64 steps by the lane that holds it (row index rml).
+    // row-m sum (Viterbi: maximum).  Plain states: each chunk of CH steps
+    // in T, then FP64.  Rescaled states: the absorbing row's Dh, flushed
+    // into FP64 every CH steps by the lane that holds it (row index rml).
+    constexpr int CH = ring_chunk(P);
     double acc = 0.0;
     const int rml = m - base;
     // steps run in pairs; a step past the last column only meets PAD columns
@@ -770,9 +780,9 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     const int total = HAT ? (nmax + P + 2) & ~1 : (nmax + P) & ~1;
     const char *ebase_lane = E + lane * 8;
 
-    for (int s0 = 0; s0 < total; s0 += kChunk) {
-        uint32_t ahead[kChunk / P];
-        ring_load<P>(ahead, s0 / kChunk + 2, hap, n, t);
+    for (int s0 = 0; s0 < total; s0 += CH) {
+        uint32_t ahead[RingPer<P>::N];
+        ring_load<P>(ahead, s0 / CH + 2, hap, n, t);
         if constexpr (W) {
             // lane t stages the boundary row at column s0 + 1 + t, which
             // lane 0 takes at step s0 + t (zero in window 0: the row-0
@@ -790,8 +800,8 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             top[128 + t] = v2;
             __syncthreads();
         }
-        const uint16_t *hp = ring + ((s0 - t) & (kRing - 1));
-        const int cnt = min(kChunk, total - s0);
+        const uint16_t *hp = ring + ((s0 - t) & (4 * CH - 1));
+        const int cnt = min(CH, total - s0);
         T la[C::KP], lb[C::KP];
         load_lam<T, P, K>(la, ebase_lane + hp[0]);
         if constexpr (HAT) {
@@ -842,7 +852,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             else
                 acc += (double)part;
         }
-        ring_store<P>(ring, s0 / kChunk + 2, ahead, t, C::CODE_BYTES);
+        ring_store<P>(ring, s0 / CH + 2, ahead, t, C::CODE_BYTES);
         __syncthreads();
     }
 

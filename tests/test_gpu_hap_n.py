@@ -10,8 +10,9 @@ oracle element by element:
 * about 3% N at random haplotype positions;
 * an all-N haplotype;
 * N in the first column, the last column (next to the PAD columns that
-  follow a haplotype), and at the 64-column chunk edges of the haplotype
-  ring (columns 64, 65, 128, 129).
+  follow a haplotype), and at the chunk edges of the haplotype ring (chunks
+  of 32 columns for groups of up to 32 lanes, 64 for 64-lane groups:
+  columns 32, 33, 64, 65, 96, 97, 128, 129).
 
 Codes above 4 are read as N by the kernels (ph_validate reports them): a
 problem with such codes must give bit-identical results to the same problem
@@ -25,7 +26,7 @@ from gpu_util import (TOL32, binding, check_against_oracle, check_plain_against_
 
 pytestmark = pytest.mark.gpu
 
-EDGE_COLS = (0, 63, 64, 127, 128)  # 0-based: columns 1, 64, 65, 128, 129
+EDGE_COLS = (0, 31, 32, 63, 64, 95, 96, 127, 128)  # 0-based: columns 1, 32, 33, 64, 65, 96, 97, 128, 129
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -93,7 +94,7 @@ def test_forward_hap_n_every_group_size(force_p):
     """Forward in every lane group size, FP32 and the FP64 rescue (forced for
     every pair), against the oracle."""
     ms = _lengths_for(force_p)
-    prob = hap_n_problem(70 + force_p, [ms[::2], ms[1::2]], [[1, 5, 64, 65, 130, 300], [2, 66, 129, 700]])
+    prob = hap_n_problem(70 + force_p, [ms[::2], ms[1::2]], [[1, 5, 32, 64, 65, 130, 300], [2, 33, 66, 97, 129, 700]])
     say(f"hap N, P={force_p}: {prob.num_pairs} pairs, read lengths {ms}, "
         f"{int((prob.hap_bases == 4).sum())} N of {len(prob.hap_bases)} haplotype bases")
     ref = oracle.forward(prob)
@@ -109,7 +110,7 @@ def test_forward_hap_n_default_bins_single_and_plain():
     """The tuned bins (groups of 4, 8, 16 and 64 lanes), one persistent launch
     over the bins (reads up to 255) and the plain single-bin kernel."""
     ms = [1, 3, 15, 16, 23, 24, 40, 51, 52, 63, 64, 80, 100, 150, 223, 224, 250, 255, 256, 400, 700, 1023]
-    prob = hap_n_problem(80, [ms[::2], ms[1::2]], [[1, 64, 65, 129, 333], [3, 128, 250, 900]])
+    prob = hap_n_problem(80, [ms[::2], ms[1::2]], [[1, 33, 64, 65, 129, 333], [3, 32, 96, 128, 250, 900]])
     ref = oracle.forward(prob)
     say(f"hap N, default bins: {prob.num_pairs} pairs")
     for kw in (dict(), dict(use_graph=False)):

@@ -176,19 +176,20 @@ def _ragged(seed, lens_m, lens_n, related=True):
 
 RAGGED_M = [1, 2, 15, 16, 17, 31, 32, 47, 63, 64, 100, 127, 128, 150, 191, 200, 239, 240, 255, 256,
             300, 319, 320, 511, 512, 700, 1023]
-RAGGED_N = [1, 2, 3, 63, 64, 65, 127, 128, 129, 300, 1000, 1100]
+RAGGED_N = [1, 2, 3, 31, 32, 33, 63, 64, 65, 95, 96, 97, 127, 128, 129, 300, 1000, 1100]
 
 
 def test_ragged_lengths_every_bin():
     """Reads at every bin edge (15/16, 31/32, ..., 255/256, 319/320, 1023),
-    haplotypes around the 64-column ring chunks, a 1x1 pair and empty
-    batches, through the default bins, the eager path and 64-lane groups."""
+    haplotypes around the ring chunks (32 columns, 64 in 64-lane groups), a
+    1x1 pair and empty batches, through the default bins, the eager path and
+    64-lane groups."""
     say("ragged lengths")
     ms, ns = RAGGED_M, RAGGED_N
     lens_m = [ms[:9], ms[9:18], ms[18:], [1], [], [5, 7]]
-    lens_n = [ns[:4], ns[3:8], ns[7:], [1], [10, 20], []]
+    lens_n = [ns[:6], ns[5:12], ns[11:], [1], [10, 20], []]
     prob = _ragged(1, lens_m, lens_n)
-    assert prob.num_pairs == 9 * 4 + 9 * 5 + 9 * 5 + 1
+    assert prob.num_pairs == 9 * 6 + 9 * 7 + 9 * 7 + 1
     ref = oracle.forward(prob)
     for kw in (dict(), dict(use_graph=False), dict(force_p=64, use_graph=False)):
         got, st = gpu_forward(prob, **kw)

@@ -41,7 +41,7 @@ def test_viterbi_ragged_every_bin():
     say("viterbi ragged lengths")
     ms, ns = RAGGED_M, RAGGED_N
     prob = _ragged(1, [ms[:9], ms[9:18], ms[18:], [1], [], [5, 7]],
-                   [ns[:4], ns[3:8], ns[7:], [1], [10, 20], []])
+                   [ns[:6], ns[5:12], ns[11:], [1], [10, 20], []])
     ref = oracle.viterbi(prob)
     for kw in (dict(), dict(use_graph=False), dict(force_p=64, use_graph=False), dict(single_launch=True)):
         got, st = gpu_viterbi(prob, **kw)

@@ -47,7 +47,7 @@ def test_noalloc_matches_plan_two_calls():
     # first call: reads at every bin edge up to 1023, haplotypes with N, and
     # precision-stress pairs that go to both FP64 sweeps
     ms, ns = RAGGED_M, RAGGED_N
-    big = _ragged(11, [ms[:9], ms[9:18], ms[18:]], [ns[:4], ns[3:8], ns[7:]])
+    big = _ragged(11, [ms[:9], ms[9:18], ms[18:]], [ns[:6], ns[5:12], ns[11:]])
     rng = np.random.default_rng(11)
     hn = rng.random(len(big.hap_bases)) < 0.03
     big.hap_bases[hn] = 4
