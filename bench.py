@@ -25,18 +25,22 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Forward GCUPS on 1 MI355X (binned FP32+FP64 rescue vs plain); adjoint GCUPS"
 FLOPS_PER_CELL = 11            # Eq. (1)-(3): 7 multiplications + 4 additions
-VALU_PER_CELL = 5              # FP32 instructions per cell of the rescaled-state sweep (4 FMA + 1 MUL)
+# FP32 issue slots per cell of the rescaled-state sweep: 4 FMA + 1 MUL, where on gfx950 an FP32 FMA
+# issues 16 lanes per clock per SIMD and an FP32 multiply 32 (measured with a microkernel of independent
+# chains), so the multiply takes half an FMA slot
+FMA_SLOTS_PER_CELL = 4.5
 VITERBI_VALU_PER_CELL = 8      # the max-product cell: 5 MUL + 3 MAX
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector peak
-PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes/clk x clock
+PEAK_FMA_LANE_OPS = 256 * 4 * 16 * 2.4e9  # unpacked FP32 FMA: CUs x SIMDs x lanes/clk x clock
 
 
 # HBM traffic of the FP32 sweep stage, from the committed rocprofv3 counter
 # summary; reported only while the forward kernel sources are the ones the
 # counters were taken on
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fwd32_hbm_traffic_mixed-2000regions.txt")
-FORWARD_SOURCES = ("paper_2411_11547_amd/csrc/ph_kernels.hip", "paper_2411_11547_amd/csrc/ph_device.h")
+FORWARD_SOURCES = ("paper_2411_11547_amd/csrc/ph_kernels.hip", "paper_2411_11547_amd/csrc/ph_device.h",
+                   "paper_2411_11547_amd/csrc/ph_internal.h")
 
 
 def log(*a):
@@ -405,7 +409,8 @@ def main():
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(prob.name),
             "kernel": "FP32 sweep stage (k_fwd32 over all length bins)",
             "kernel_ms": round(float(st_mean[1]), 4),
-            "valu_slot_frac": round(VALU_PER_CELL * cells / t32 / PEAK_VALU_LANE_OPS, 4)}
+            "fma_slots_per_cell": FMA_SLOTS_PER_CELL,
+            "fma_slot_frac": round(FMA_SLOTS_PER_CELL * cells / t32 / PEAK_FMA_LANE_OPS, 4)}
 
     uniform = None if args.no_uniform else uniform_report()
     precision = None if args.no_precision else precision_report()
