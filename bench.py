@@ -36,11 +36,11 @@ PEAK_FMA_LANE_OPS = 256 * 4 * 16 * 2.4e9  # unpacked FP32 FMA: CUs x SIMDs x lan
 
 
 # HBM traffic of the FP32 sweep stage, from the committed rocprofv3 counter
-# summary; reported only while the forward kernel sources are the ones the
-# counters were taken on
+# summary; reported only while the forward kernel sources and the bin table
+# are the ones the counters were taken on
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fwd32_hbm_traffic_mixed-2000regions.txt")
 FORWARD_SOURCES = ("paper_2411_11547_amd/csrc/ph_kernels.hip", "paper_2411_11547_amd/csrc/ph_device.h",
-                   "paper_2411_11547_amd/csrc/ph_internal.h")
+                   "paper_2411_11547_amd/csrc/ph_internal.h", "paper_2411_11547_amd/tune_gfx950.txt")
 
 
 def log(*a):

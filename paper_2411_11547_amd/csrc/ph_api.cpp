@@ -63,9 +63,20 @@ namespace {
         if (e_ != hipSuccess) return fail(PH_ERR_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
     } while (0)
 
+// One bin of the FP32 sweep: reads up to max_m bases in groups of P lanes x
+// K rows.  A table line may add a haplotype-length split "n_split P2 K2":
+// pairs of that read range whose haplotype has at least n_split bases go to
+// a second bin of P2 x K2 (an entry with alt = true that follows its parent,
+// with the same max_m).
 struct TuneEntry {
     int max_m, P, K;
+    int n_split = 0, P2 = 0, K2 = 0;
+    bool alt = false;
 };
+
+// haplotype-length bucket of the binning key (16-column buckets below 1024,
+// 128-column buckets above; the kernels' pair_key uses the same)
+int hap_bucket(int64_t n) { return n < 1024 ? (int)(n >> 4) : 64 + (int)std::min<int64_t>((n - 1024) >> 7, 63); }
 
 constexpr int kSideStreams = 4;
 constexpr int kStageEvents = 5;
@@ -125,12 +136,26 @@ ph_status read_table(const char *path, std::vector<TuneEntry> &t)
     t.clear();
     while (std::getline(f, line)) {
         if (line.empty() || line[0] == '#') continue;
-        std::istringstream ss(line);
+        const std::string body = line.substr(0, line.find('#'));
+        std::istringstream ss(body);
         TuneEntry e;
         if (!(ss >> e.max_m >> e.P >> e.K)) return fail(PH_ERR_INVALID, "bad tune line: %s", line.c_str());
         if (!fwd32_supported(e.P, e.K)) return fail(PH_ERR_UNSUPPORTED, "tune entry P=%d K=%d not compiled", e.P, e.K);
         if (e.max_m > e.P * e.K - 1 || e.max_m < 1)
             return fail(PH_ERR_INVALID, "tune entry max_m=%d exceeds P*K-1 for P=%d K=%d", e.max_m, e.P, e.K);
+        if (ss >> e.n_split) {
+            if (!(ss >> e.P2 >> e.K2) || e.n_split < 1)
+                return fail(PH_ERR_INVALID, "bad haplotype-length split in tune line: %s", line.c_str());
+            if (!fwd32_supported(e.P2, e.K2))
+                return fail(PH_ERR_UNSUPPORTED, "tune entry P=%d K=%d not compiled", e.P2, e.K2);
+            if (e.max_m > e.P2 * e.K2 - 1)
+                return fail(PH_ERR_INVALID, "tune entry max_m=%d exceeds P*K-1 for P=%d K=%d", e.max_m, e.P2, e.K2);
+            const bool edge = e.n_split < 1024 ? e.n_split % 16 == 0
+                                               : (e.n_split - 1024) % 128 == 0 && e.n_split <= 1024 + 63 * 128;
+            if (!edge)
+                return fail(PH_ERR_INVALID, "haplotype-length split %d is not a bucket edge (a multiple of 16 "
+                            "below 1024, 1024 + a multiple of 128 up to 9088)", e.n_split);
+        }
         t.push_back(e);
     }
     std::sort(t.begin(), t.end(), [](const TuneEntry &a, const TuneEntry &b) { return a.max_m < b.max_m; });
@@ -138,12 +163,25 @@ ph_status read_table(const char *path, std::vector<TuneEntry> &t)
     // neighbouring ranges with the same configuration form one bin
     std::vector<TuneEntry> merged;
     for (const TuneEntry &e : t) {
-        if (!merged.empty() && merged.back().P == e.P && merged.back().K == e.K)
+        const TuneEntry *b = merged.empty() ? nullptr : &merged.back();
+        if (b && b->P == e.P && b->K == e.K && b->n_split == e.n_split && b->P2 == e.P2 && b->K2 == e.K2)
             merged.back().max_m = e.max_m;
         else
             merged.push_back(e);
     }
-    t.swap(merged);
+    // each split adds its second bin right after its parent
+    t.clear();
+    for (const TuneEntry &e : merged) {
+        t.push_back(e);
+        if (e.n_split) {
+            TuneEntry a;
+            a.max_m = e.max_m;
+            a.P = e.P2;
+            a.K = e.K2;
+            a.alt = true;
+            t.push_back(a);
+        }
+    }
     if ((int)t.size() > kMaxBins - 1)
         return fail(PH_ERR_INVALID, "tune table has more than %d distinct bins", kMaxBins - 1);
     return PH_OK;
@@ -172,6 +210,8 @@ struct ph_plan {
     float *d_bnd32 = nullptr;
     double *d_bnd64 = nullptr;
     int32_t *d_long_rescue = nullptr;
+    int split_at = -1;     // offset of the haplotype-length split table in d_m2bin (-1: none)
+    std::vector<std::pair<int, int>> launch_order;  // FP32 stage: (bin, side stream) in launch order
     bool single = false;   // one persistent FP32 launch over all bins
     int single_grid = 0;
 
@@ -513,12 +553,8 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     p->nhap_bases = ho[nh];
     p->max_m = max_m;
     p->max_n = max_n;
-    HIPCHK(hipGetDevice(&p->device));
-    HIPCHK(hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device));
-    std::call_once(g_lut_once, [] { g_lut_status = upload_luts(); });
-    HIPCHK(g_lut_status);
 
-    // --- length bins ----------------------------------------------------------
+    // --- length bins (host only: a bad table is reported before any GPU call) --
     if (opts.tune_table_path) {
         ph_status st = read_table(opts.tune_table_path, p->table);
         if (st != PH_OK) return st;
@@ -527,6 +563,10 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     } else {
         p->table = default_table(opts.force_p);
     }
+    HIPCHK(hipGetDevice(&p->device));
+    HIPCHK(hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device));
+    std::call_once(g_lut_once, [] { g_lut_status = upload_luts(); });
+    HIPCHK(g_lut_status);
     if (max_m > kMaxReadLen) {
         // the longest bin: 64 lanes x 16 rows per window, never tuned
         if (opts.plain) return fail(PH_ERR_UNSUPPORTED, "plain mode supports reads up to %d bases", kMaxReadLen);
@@ -547,6 +587,16 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     }
     std::vector<int32_t> binG(nbins);
     for (int b = 0; b < nbins; ++b) binG[b] = 64 / p->table[nbins - 1 - b].P;
+    // haplotype-length splits: split[b] = first bucket sent to bin split[kMaxBins + b]
+    // (kBuckets: none); the alt entry follows its parent, so its bin is b - 1
+    std::vector<int16_t> split(2 * kMaxBins, 0);
+    bool any_split = false;
+    for (int b = 0; b < nbins; ++b) {
+        const TuneEntry &e = p->table[nbins - 1 - b];
+        split[b] = (int16_t)(e.n_split ? hap_bucket(e.n_split) : kBuckets);
+        split[kMaxBins + b] = (int16_t)(e.n_split ? b - 1 : b);
+        any_split = any_split || e.n_split;
+    }
     p->bin_pairs.assign(nbins, 0);
     int64_t cells = 0;
     for (int32_t q = 0; q < nb; ++q) {
@@ -556,7 +606,14 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
         for (int32_t r = rb[q]; r < rb[q + 1]; ++r) {
             const int m = (int)(ro[r + 1] - ro[r]);
             const int bin = m2bin[std::min(m, kMaxReadLen + 1)];
-            p->bin_pairs[bin] += H;
+            if (split[bin] < kBuckets) {
+                int64_t over = 0;
+                for (int32_t h = hb[q]; h < hb[q + 1]; ++h) over += hap_bucket(ho[h + 1] - ho[h]) >= split[bin];
+                p->bin_pairs[bin] += H - over;
+                p->bin_pairs[split[kMaxBins + bin]] += over;
+            } else {
+                p->bin_pairs[bin] += H;
+            }
             cells += (int64_t)m * nsum;
             if (bin == p->long_bin) {  // every pair of the long bin gets a boundary slot
                 p->long_pairs += H;
@@ -568,6 +625,11 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
         }
     }
     p->cells = cells;
+    // the split table travels behind the length map in the same device array
+    if (any_split) {
+        p->split_at = (int)m2bin.size();
+        m2bin.insert(m2bin.end(), split.begin(), split.end());
+    }
     p->bin_grid.assign(nbins, 0);
     for (int b = 0; b < nbins; ++b) {
         if (!p->bin_pairs[b] || b == p->long_bin) continue;
@@ -575,6 +637,23 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
         const int64_t tiles = (p->bin_pairs[b] + binG[b] - 1) / binG[b];
         const int64_t cap = (int64_t)p->cus * fwd32_blocks_per_cu(e.P, e.K);
         p->bin_grid[b] = (int)std::min<int64_t>(tiles, cap);
+    }
+    // side streams of the bin kernels: the long-read bin first, then the bins
+    // longest reads first, round-robin, so that every stream starts with its
+    // longest tiles; the second bin of a haplotype-length split runs on its
+    // parent's stream just before it and takes no turn of its own (a turn
+    // would move every later bin to another stream).  Balancing the streams'
+    // estimated work instead, largest first, was 6% slower on the mixed batch.
+    {
+        p->launch_order.clear();
+        int next = 0;
+        if (p->long_pairs) p->launch_order.push_back({p->long_bin, next++ % kSideStreams});
+        for (int b = 0; b < nbins; ++b) {
+            if (!p->bin_grid[b]) continue;
+            const bool alt = p->table[nbins - 1 - b].alt;
+            p->launch_order.push_back({b, next % kSideStreams});
+            if (!alt) ++next;
+        }
     }
     if (p->long_pairs) {
         p->long_grid = (int)std::min<int64_t>(p->long_pairs, (int64_t)p->cus * long32_blocks_per_cu());
@@ -674,6 +753,7 @@ BinArgs bin_args(ph_plan *p, const ph_problem *pb)
     a.read_offset = pb->read_offset;
     a.hap_offset = pb->hap_offset;
     a.m2bin = p->d_m2bin;
+    a.split = p->split_at >= 0 ? p->d_m2bin + p->split_at : nullptr;
     a.num_bins = (int32_t)p->table.size();
     a.bin_G = p->d_bin_G;
     a.hist = p->d_hist;
@@ -741,27 +821,23 @@ ph_status enqueue_stage(ph_plan *p, int stage, const ph_problem *pb, const float
         } else if (p->single && !viterbi) {
             HIPCHK(launch_fwd32_single(sa, p->single_grid, s));
         } else {
-            // bins longest first, round-robin over side streams forked from s;
-            // the windows of the long bin run in order on one stream
+            // the bins on side streams forked from s, in the plan's launch
+            // order; the windows of the long bin run in order on one stream
             HIPCHK(hipEventRecord(p->fork, s));
             bool used[kSideStreams] = {};
-            int next = 0;
-            if (p->long_pairs) {
-                const int k = next++ % kSideStreams;
-                HIPCHK(hipStreamWaitEvent(p->side[k], p->fork, 0));
-                used[k] = true;
-                SweepArgs la = sa;
-                la.bnd = p->d_bnd32;
-                for (int w = 0; w < p->windows; ++w) HIPCHK(launch_long32(la, w, p->long_grid, p->side[k]));
-            }
-            for (int b = 0; b < sa.num_bins; ++b) {
-                if (!p->bin_grid[b]) continue;
-                const int k = next++ % kSideStreams;
+            for (const auto &bk : p->launch_order) {
+                const int b = bk.first, k = bk.second;
                 if (!used[k]) {
                     HIPCHK(hipStreamWaitEvent(p->side[k], p->fork, 0));
                     used[k] = true;
                 }
-                HIPCHK(launch_fwd32(sa, sa.bins[b].P, sa.bins[b].K, b, p->bin_grid[b], p->side[k]));
+                if (b == p->long_bin && p->long_pairs) {
+                    SweepArgs la = sa;
+                    la.bnd = p->d_bnd32;
+                    for (int w = 0; w < p->windows; ++w) HIPCHK(launch_long32(la, w, p->long_grid, p->side[k]));
+                } else {
+                    HIPCHK(launch_fwd32(sa, sa.bins[b].P, sa.bins[b].K, b, p->bin_grid[b], p->side[k]));
+                }
             }
             for (int k = 0; k < kSideStreams; ++k) {
                 if (!used[k]) continue;

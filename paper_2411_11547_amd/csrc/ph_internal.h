@@ -86,6 +86,9 @@ struct BinArgs {
     const int32_t *batch_read_begin, *batch_hap_begin;
     const int64_t *read_offset, *hap_offset;
     const int16_t *m2bin;        // [kMaxReadLen+2]
+    // haplotype-length splits or NULL: split[b] = first haplotype-length
+    // bucket whose pairs go to bin split[kMaxBins + b] instead of bin b
+    const int16_t *split;
     int32_t num_bins;
     const int32_t *bin_G;        // pairs per tile of each bin
     int32_t *hist;               // [kMaxKeys]

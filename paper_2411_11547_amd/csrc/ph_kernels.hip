@@ -1065,8 +1065,9 @@ __device__ __forceinline__ int pair_key(const BinArgs &a, int64_t k, PairRec &re
     rec.hap = h;
     rec.out = (int)k;
     rec.n = n;
-    const int b = a.m2bin[m > kMaxReadLen ? kMaxReadLen + 1 : m];
+    int b = a.m2bin[m > kMaxReadLen ? kMaxReadLen + 1 : m];
     const int nb = n < 1024 ? (n >> 4) : 64 + min((n - 1024) >> 7, 63);
+    if (a.split && nb >= a.split[b]) b = a.split[kMaxBins + b];
     return b * kBuckets + (kBuckets - 1 - nb);
 }
 

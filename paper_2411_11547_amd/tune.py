@@ -92,31 +92,36 @@ def time_config(prob, dev, m, P, K, steps=3):
 
 
 def read_table(path):
-    """[(max_m, P, K, alternatives)] from a table file; alternatives are the
-    stage-1 (GCUPS, P, K) entries of the line's comment, best first."""
+    """[(max_m, P, K, alternatives, line, split)] from a table file;
+    alternatives are the stage-1 (GCUPS, P, K) entries of the line's comment,
+    best first; split is the line's haplotype-length split "n_split P2 K2"
+    (pairs of the range with haplotypes of at least n_split bases go to a bin
+    of P2 x K2), kept as written, or ""."""
     rows = []
     with open(path) as f:
         for line in f:
             if not line.strip() or line.startswith("#"):
                 continue
             body, _, comment = line.partition("#")
-            m, P, K = (int(x) for x in body.split())
+            nums = [int(x) for x in body.split()]
+            m, P, K = nums[:3]
+            split = " ".join(str(x) for x in nums[3:6])
             alts = []
             for tok in comment.split():
                 if "x" in tok and ":" in tok:
                     pk, g = tok.split(":")
                     p, k = pk.split("x")
                     alts.append((float(g), int(p), int(k)))
-            rows.append([m, P, K, sorted(alts, reverse=True), line.rstrip("\n")])
+            rows.append([m, P, K, sorted(alts, reverse=True), line.rstrip("\n"), split])
     return rows
 
 
 def write_table(rows, path, header):
     with open(path, "w") as f:
         f.write("\n".join(header) + "\n")
-        for m, P, K, alts, line in rows:
+        for m, P, K, alts, line, split in rows:
             desc = " ".join(f"{p}x{k}:{g:.0f}" for g, p, k in alts)
-            f.write(f"{m} {P} {K}  # {desc}\n")
+            f.write(f"{m} {P} {K}{' ' + split if split else ''}  # {desc}\n")
 
 
 def time_table(rows, prob, dev, steps):
@@ -124,7 +129,7 @@ def time_table(rows, prob, dev, steps):
     import torch
     from . import binding
     with tempfile.NamedTemporaryFile("w", suffix=".txt", delete=False) as f:
-        f.write("".join(f"{m} {P} {K}\n" for m, P, K, _, _ in rows))
+        f.write("".join(f"{m} {P} {K} {split}\n" for m, P, K, _, _, split in rows))
         path = f.name
     try:
         plan = binding.Plan(prob, tune_table=path)

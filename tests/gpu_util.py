@@ -20,6 +20,19 @@ def say(*a):
     print(*a, flush=True)
 
 
+def gpu_viterbi(prob, log10_params=None, **plan_kw):
+    """The max-product score through a plan (ph_viterbi_batch)."""
+    import torch
+    dev = binding.DeviceProblem(prob)
+    plan = binding.Plan(prob, **plan_kw)
+    lp = None if log10_params is None else torch.from_numpy(np.ascontiguousarray(log10_params, np.float32)).cuda()
+    out, st = plan.viterbi(dev, lp)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().copy(), st.cpu().numpy().copy()
+    plan.close()
+    return res
+
+
 def gpu_forward(prob, log10_params=None, **plan_kw):
     import torch
     dev = binding.DeviceProblem(prob)

@@ -162,3 +162,27 @@ def test_noalloc_rejects_sizes_beyond_its_maximum():
     pb = binding.PhProblem(1, None, None, 2, None, None, None, None, None, None, 1, None, None)
     st = binding.load().ph_forward_batch_noalloc(ctypes.byref(shape), ctypes.byref(pb), None, None, None, None)
     assert st == -5
+
+
+def test_tune_table_validation(tmp_path):
+    """A bin table is read before any GPU call: unknown configurations,
+    ranges that do not fit, and haplotype-length splits that are malformed or
+    not at an edge of the binning key's buckets are rejected."""
+    good = wl.from_strings([(["ACGT"], ["ACGTT"])])
+    cases = [("63 16 4\n1023 64 16\n", None),
+             ("63 16 4 512 64 1\n1023 64 16\n", "not compiled"),
+             ("63 16 4 500 64 2\n1023 64 16\n", "bucket edge"),
+             ("63 16 4 1100 64 2\n1023 64 16\n", "bucket edge"),
+             ("63 16 4 1024 64\n1023 64 16\n", "bad haplotype-length split"),
+             ("63 16 4 1024 32 1\n1023 64 16\n", "not compiled"),
+             ("200 16 4\n1023 64 16\n", "exceeds P*K-1"),
+             ("63 16 4 1152 64 2  # comment 64x4:1\n1023 64 16\n", None)]
+    for text, err in cases:
+        path = tmp_path / "t.txt"
+        path.write_text(text)
+        st, msg = _plan_status(good, tune_table_path=str(path).encode())
+        if err is None:
+            # a valid table: plan creation goes on to the GPU, which this host lacks
+            assert "table" not in msg and "split" not in msg, (text, msg)
+        else:
+            assert st in (-1, -2) and err in msg, (text, st, msg)

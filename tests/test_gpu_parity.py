@@ -8,7 +8,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_util import TOL32, TOL64, binding, check_against_oracle, gpu_forward, oracle, say, wl
+from gpu_util import TOL32, TOL64, binding, check_against_oracle, gpu_forward, gpu_viterbi, oracle, say, wl
 
 pytestmark = pytest.mark.gpu
 
@@ -194,6 +194,25 @@ def test_ragged_lengths_every_bin():
     for kw in (dict(), dict(use_graph=False), dict(force_p=64, use_graph=False)):
         got, st = gpu_forward(prob, **kw)
         check_against_oracle(prob, got, st, ref=ref)
+
+
+def test_haplotype_length_split_bins(tmp_path):
+    """A bin table line may send the pairs of its read range whose haplotype
+    reaches a length to a second bin (the committed table: reads 240-255 in
+    16 x 16 below 1024 haplotype bases, 64 x 4 from there).  Haplotypes on
+    both sides of that edge and of a lower split, through the committed
+    table, a table splitting at 256, and the Viterbi score."""
+    say("haplotype-length split bins")
+    ns = [100, 255, 256, 257, 1008, 1023, 1024, 1025, 1151, 1152, 2000]
+    prob = _ragged(61, [[240, 247, 255], [250, 200], [255]], [ns[:6], ns[5:], [1024, 1023]])
+    ref = oracle.forward(prob)
+    split = tmp_path / "split.txt"
+    split.write_text("223 16 14\n255 16 16 256 32 8\n1023 64 16\n")
+    for kw in (dict(), dict(tune_table=str(split)), dict(tune_table=str(split), use_graph=False)):
+        got, st = gpu_forward(prob, **kw)
+        check_against_oracle(prob, got, st, ref=ref)
+    got, st = gpu_viterbi(prob)
+    check_against_oracle(prob, got, st, ref=oracle.viterbi(prob))
 
 
 def test_gap_continuation_zero_rows():

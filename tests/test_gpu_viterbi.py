@@ -4,7 +4,7 @@ the FP64 oracle's max-product DP; the same tolerances as the forward."""
 import numpy as np
 import pytest
 
-from gpu_util import binding, check_against_oracle, oracle, say, wl
+from gpu_util import binding, check_against_oracle, gpu_viterbi, oracle, say, wl
 from test_gpu_long import long_problem
 from test_gpu_parity import RAGGED_M, RAGGED_N, _ragged
 
@@ -16,18 +16,6 @@ def _gpu():
     import torch
     assert torch.cuda.is_available(), "GPU tests need an MI355X"
     yield
-
-
-def gpu_viterbi(prob, log10_params=None, **plan_kw):
-    import torch
-    dev = binding.DeviceProblem(prob)
-    plan = binding.Plan(prob, **plan_kw)
-    lp = None if log10_params is None else torch.from_numpy(np.ascontiguousarray(log10_params, np.float32)).cuda()
-    out, st = plan.viterbi(dev, lp)
-    torch.cuda.synchronize()
-    res = out.cpu().numpy().copy(), st.cpu().numpy().copy()
-    plan.close()
-    return res
 
 
 def test_viterbi_config0():

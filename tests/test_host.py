@@ -84,9 +84,16 @@ def test_committed_bin_table():
     assert entries, "empty table"
     max_m = [e[0] for e in entries]
     assert max_m == sorted(max_m) and len(set(max_m)) == len(max_m) and max_m[-1] == 1023
-    for m, p, k in entries:
-        assert (p, k) in tune.CONFIGS, (m, p, k)
-        assert p * k - 1 >= m, (m, p, k)  # the absorbing row fits
+    for e in entries:
+        assert len(e) in (3, 6), e
+        m = e[0]
+        for p, k in (e[1:3], e[3 + 1:6]) if len(e) == 6 else (e[1:3],):
+            assert (p, k) in tune.CONFIGS, e
+            assert p * k - 1 >= m, e  # the absorbing row fits
+        if len(e) == 6:  # a haplotype-length split at a bucket edge of the binning key
+            assert (e[3] < 1024 and e[3] % 16 == 0) or (e[3] >= 1024 and (e[3] - 1024) % 128 == 0), e
+    rows = tune.read_table(tune.DEFAULT_TABLE)
+    assert [r[0] for r in rows] == max_m
 
 
 def test_bench_refuses_more_than_one_gpu():
