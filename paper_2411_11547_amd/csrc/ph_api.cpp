@@ -66,12 +66,11 @@ namespace {
 // One bin of the FP32 sweep: reads up to max_m bases in groups of P lanes x
 // K rows.  A table line may add a haplotype-length split "n_split P2 K2":
 // pairs of that read range whose haplotype has at least n_split bases go to
-// a second bin of P2 x K2 (an entry with alt = true that follows its parent,
-// with the same max_m).
+// a second bin of P2 x K2 (a table entry that follows its parent, with the
+// same max_m, so that the read-length map never selects it).
 struct TuneEntry {
     int max_m, P, K;
     int n_split = 0, P2 = 0, K2 = 0;
-    bool alt = false;
 };
 
 // haplotype-length bucket of the binning key (16-column buckets below 1024,
@@ -178,7 +177,6 @@ ph_status read_table(const char *path, std::vector<TuneEntry> &t)
             a.max_m = e.max_m;
             a.P = e.P2;
             a.K = e.K2;
-            a.alt = true;
             t.push_back(a);
         }
     }
@@ -640,20 +638,14 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     }
     // side streams of the bin kernels: the long-read bin first, then the bins
     // longest reads first, round-robin, so that every stream starts with its
-    // longest tiles; the second bin of a haplotype-length split runs on its
-    // parent's stream just before it and takes no turn of its own (a turn
-    // would move every later bin to another stream).  Balancing the streams'
-    // estimated work instead, largest first, was 6% slower on the mixed batch.
+    // longest tiles.  (Balancing the streams' estimated work instead, largest
+    // first, was 6% slower on the mixed batch.)
     {
         p->launch_order.clear();
         int next = 0;
         if (p->long_pairs) p->launch_order.push_back({p->long_bin, next++ % kSideStreams});
-        for (int b = 0; b < nbins; ++b) {
-            if (!p->bin_grid[b]) continue;
-            const bool alt = p->table[nbins - 1 - b].alt;
-            p->launch_order.push_back({b, next % kSideStreams});
-            if (!alt) ++next;
-        }
+        for (int b = 0; b < nbins; ++b)
+            if (p->bin_grid[b]) p->launch_order.push_back({b, next++ % kSideStreams});
     }
     if (p->long_pairs) {
         p->long_grid = (int)std::min<int64_t>(p->long_pairs, (int64_t)p->cus * long32_blocks_per_cu());

@@ -199,12 +199,13 @@ def test_ragged_lengths_every_bin():
 def test_haplotype_length_split_bins(tmp_path):
     """A bin table line may send the pairs of its read range whose haplotype
     reaches a length to a second bin (the committed table: reads 240-255 in
-    16 x 16 below 1024 haplotype bases, 64 x 4 from there).  Haplotypes on
-    both sides of that edge and of a lower split, through the committed
-    table, a table splitting at 256, and the Viterbi score."""
+    16 x 16 below 2048 haplotype bases, 64 x 4 from there).  Haplotypes on
+    both sides of that edge and of a lower one, through the committed table,
+    a table splitting at 256 and the Viterbi score, and batches where one
+    side holds only a few pairs."""
     say("haplotype-length split bins")
-    ns = [100, 255, 256, 257, 1008, 1023, 1024, 1025, 1151, 1152, 2000]
-    prob = _ragged(61, [[240, 247, 255], [250, 200], [255]], [ns[:6], ns[5:], [1024, 1023]])
+    ns = [100, 255, 256, 257, 1008, 1023, 1024, 2047, 2048, 2049, 2176]
+    prob = _ragged(61, [[240, 247, 255], [250, 200], [255]], [ns[:6], ns[5:], [2048, 2047]])
     ref = oracle.forward(prob)
     split = tmp_path / "split.txt"
     split.write_text("223 16 14\n255 16 16 256 32 8\n1023 64 16\n")
@@ -213,6 +214,10 @@ def test_haplotype_length_split_bins(tmp_path):
         check_against_oracle(prob, got, st, ref=ref)
     got, st = gpu_viterbi(prob)
     check_against_oracle(prob, got, st, ref=oracle.viterbi(prob))
+    for lens_n in ([[300] * 12 + [2100]] * 2, [[2100] * 12 + [300]] * 2):  # 3 of 39 pairs long, or short
+        prob = _ragged(62, [[240, 250], [255]], lens_n)
+        got, st = gpu_forward(prob)
+        check_against_oracle(prob, got, st, ref=oracle.forward(prob))
 
 
 def test_gap_continuation_zero_rows():
