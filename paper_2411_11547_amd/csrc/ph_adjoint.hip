@@ -175,6 +175,125 @@ struct AdjPair {
     const uint8_t *hs;   // staged haplotype codes (PAD outside 1..n); column j at hs[j + P]
     T *ckl;              // FP32: the wave's LDS checkpoint buffer [3K+3][64], after the staged haplotypes
 
+    // The lane's K rows, rescaled states: coefficients into registers and
+    // emissions into the lane's column of the table.  The quality bytes of
+    // the K rows (and of the rows on either side) are all requested before
+    // any is used, so the tile waits for memory once, not once per row.
+    __device__ __forceinline__ void init_rows_hat(const AdjArgs &A, char *mine)
+    {
+        const DevProblem &pb = A.pb;
+        const double *L = A.lin_params;
+        // Phred mode: the quality bytes of rows base-1 .. base+K, all loads
+        // issued at once; the table lookups that follow hit the cache
+        uint32_t qb[K], qi[K], qd[K], qg[K], qgn[K], qdp[K], code[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int i = t * K + r;
+            const int64_t pos = ro + min(i, m - 1);
+            code[r] = pb.read_bases[pos];
+            if (!L) {
+                qb[r] = pb.bq[pos];
+                qi[r] = pb.iq[pos];
+                qd[r] = pb.dq[pos];
+                qg[r] = pb.gq[pos];
+                qgn[r] = pb.gq[ro + min(i + 1, m - 1)];
+                qdp[r] = pb.dq[ro + max(min(i - 1, m - 1), 0)];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int i = t * K + r;
+            const int64_t pos = ro + min(i, m - 1);
+            double pa, pbt, pd, pe, plm, plx, bnx, zpv;
+            if (L) {
+                const double *q = L + pos * 8;
+                pa = q[0];
+                pbt = q[1];
+                pd = q[2];
+                pe = q[3];
+                plm = q[5];
+                plx = q[6];
+                bnx = L[(ro + min(i + 1, m - 1)) * 8 + 1];
+                zpv = L[(ro + max(min(i - 1, m - 1), 0)) * 8 + 4];
+            } else {
+                const double Q = c_prob[qb[r]];
+                pd = c_prob[qi[r]];
+                const double z = c_prob[qd[r]];
+                pe = c_prob[qg[r]];
+                pa = 1.0 - pd - z;
+                pbt = 1.0 - pe;
+                plm = 1.0 - Q;
+                plx = Q / 3.0;
+                bnx = 1.0 - c_prob[qgn[r]];
+                zpv = c_prob[qdp[r]];
+            }
+            const bool real = i < m;
+            const bool inner = real && i >= 1;
+            const double bn = (i + 1 < m) ? bnx : 1.0;
+            const double zp = inner ? zpv : 0.0;
+            const bool ok = pbt >= 0x1p-20;
+            bad = bad || (inner && !ok);
+            al[r] = i == 0 ? (T)0 : real ? (T)pa : (i == m ? (T)1 : (T)0);
+            cd[r] = inner ? (T)(pbt * zp) : (T)0;
+            kd[r] = inner ? (T)(bn * pd) : (T)0;
+            ke[r] = (inner && ok) ? (T)(bn * pe / pbt) : (T)0;
+            ep[r] = real ? (T)pe : (i == m ? (T)1 : (T)0);
+            const bool one = i == m;  // the absorbing row takes every column with lam = 1
+            const uint32_t cr = clamp_code(code[r]);
+#pragma unroll
+            for (int c = 0; c < kCodes; ++c) {
+                const bool match = cr == (uint32_t)c || cr == 4u || c == 4;
+                T v = one ? (T)1 : (T)0;
+                if (real && c != kPad) v = match ? (T)plm : -(T)plx;
+                *(T *)(mine + c * C::CODE_BYTES + r * C::ROW_BYTES) = v;
+            }
+        }
+    }
+
+    // The same for the plain states of the FP64 pass, one row at a time (the
+    // row parameters parked in the lane's own table entries, then loaded).
+    __device__ __forceinline__ void init_rows_plain(const AdjArgs &A, char *mine)
+    {
+        const DevProblem &pb = A.pb;
+        auto slot = [&](int c, int r) -> T * { return (T *)(mine + c * C::CODE_BYTES + r * C::ROW_BYTES); };
+#pragma unroll 1
+        for (int r = 0; r < K; ++r) {
+            const int i = t * K + r;
+            const int ic = min(i, m - 1);
+            const RowPar p = load_row(pb, A.lin_params, ro + ic, c_prob);
+            const bool real = i < m;
+            *slot(0, r) = real ? (T)p.a : (T)0;
+            *slot(1, r) = real ? (T)p.b : (T)0;
+            *slot(2, r) = real ? (T)p.d : (i == m ? (T)1 : (T)0);
+            *slot(3, r) = real ? (T)p.e : (T)1;
+            const double bnext = (i + 1 < m) ? load_beta(pb, A.lin_params, ro + i + 1, c_prob) : 0.0;
+            *slot(4, r) = real ? (T)(p.z * bnext) : (T)0;
+        }
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            al[r] = *slot(0, r);
+            be[r] = *slot(1, r);
+            de[r] = *slot(2, r);
+            ep[r] = *slot(3, r);
+            ze[r] = *slot(4, r);
+        }
+#pragma unroll 1
+        for (int r = 0; r < K; ++r) {
+            const int i = t * K + r;
+            const int ic = min(i, m - 1);
+            const RowPar p = load_row(pb, A.lin_params, ro + ic, c_prob);
+            const bool real = i < m;
+            const uint32_t code = clamp_code(pb.read_bases[ro + ic]);
+#pragma unroll
+            for (int c = 0; c < kCodes; ++c) {
+                const bool match = code == (uint32_t)c || code == 4u || c == 4;
+                T v = (T)0;
+                if (real && c != kPad) v = match ? (T)p.lm : -(T)p.lx;
+                *slot(c, r) = v;
+            }
+        }
+    }
+
     // S: forward steps of the pair's group (a multiple of the checkpoint
     // block); hs_bytes: LDS bytes per group for the staged haplotype (it
     // follows the emission table).
@@ -193,74 +312,29 @@ struct AdjPair {
         bad = false;
         E = lds;
         char *mine = E + lane * C::ENT;
-        auto slot = [&](int c, int r) -> T * { return (T *)(mine + c * C::CODE_BYTES + r * C::ROW_BYTES); };
-#pragma unroll 1
-        for (int r = 0; r < K; ++r) {
-            const int i = t * K + r;
-            const int ic = min(i, m - 1);
-            const RowPar p = load_row(pb, A.lin_params, ro + ic, c_prob);
-            const bool real = i < m;
-            if constexpr (HAT) {
-                const bool inner = real && i >= 1;
-                const double bn = (i + 1 < m) ? load_beta(pb, A.lin_params, ro + i + 1, c_prob) : 1.0;
-                const double zp = inner ? load_row(pb, A.lin_params, ro + i - 1, c_prob).z : 0.0;
-                const bool ok = p.b >= 0x1p-20;
-                bad = bad || (inner && !ok);
-                *slot(0, r) = i == 0 ? (T)0 : real ? (T)p.a : (i == m ? (T)1 : (T)0);
-                *slot(1, r) = inner ? (T)(p.b * zp) : (T)0;
-                *slot(2, r) = inner ? (T)(bn * p.d) : (T)0;
-                *slot(3, r) = (inner && ok) ? (T)(bn * p.e / p.b) : (T)0;
-                *slot(4, r) = real ? (T)p.e : (i == m ? (T)1 : (T)0);
-            } else {
-                *slot(0, r) = real ? (T)p.a : (T)0;
-                *slot(1, r) = real ? (T)p.b : (T)0;
-                *slot(2, r) = real ? (T)p.d : (i == m ? (T)1 : (T)0);
-                *slot(3, r) = real ? (T)p.e : (T)1;
-                const double bnext = (i + 1 < m) ? load_beta(pb, A.lin_params, ro + i + 1, c_prob) : 0.0;
-                *slot(4, r) = real ? (T)(p.z * bnext) : (T)0;
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < K; ++r) {
-            if constexpr (HAT) {
-                al[r] = *slot(0, r);
-                cd[r] = *slot(1, r);
-                kd[r] = *slot(2, r);
-                ke[r] = *slot(3, r);
-                ep[r] = *slot(4, r);
-            } else {
-                al[r] = *slot(0, r);
-                be[r] = *slot(1, r);
-                de[r] = *slot(2, r);
-                ep[r] = *slot(3, r);
-                ze[r] = *slot(4, r);
-            }
+        if constexpr (HAT) {
+            init_rows_hat(A, mine);
+        } else {
+            init_rows_plain(A, mine);
         }
         // D(0, j) = 1/n times the first read row's beta (it multiplies that
         // D in both forms), scaled
         edge = (t == 0) ? (T)(ldexp(load_beta(pb, A.lin_params, ro, c_prob), AdjRange<T>::kFwd) / (double)n) : (T)0;
-#pragma unroll 1
-        for (int r = 0; r < K; ++r) {
-            const int i = t * K + r;
-            const int ic = min(i, m - 1);
-            const RowPar p = load_row(pb, A.lin_params, ro + ic, c_prob);
-            const bool real = i < m;
-            const bool one = HAT && i == m;  // the absorbing row takes every column with lam = 1
-            const uint32_t code = clamp_code(pb.read_bases[ro + ic]);
-#pragma unroll
-            for (int c = 0; c < kCodes; ++c) {
-                const bool match = code == (uint32_t)c || code == 4u || c == 4;
-                T v = one ? (T)1 : (T)0;
-                if (real && c != kPad) v = match ? (T)p.lm : -(T)p.lx;
-                *(T *)(mine + c * C::CODE_BYTES + r * C::ROW_BYTES) = v;
-            }
-        }
         uint8_t *h = (uint8_t *)(lds + C::E_BYTES + g * hs_bytes);
         const uint8_t *hap = pb.hap_bases + pb.hap_offset[rec.hap];
         const int len = S + P + 2;
-        for (int x = t; x < len; x += P) {
-            const int j = x - P;
-            h[x] = (uint8_t)((j >= 1 && j <= n) ? clamp_code(hap[j - 1]) : (uint32_t)kPad);
+        // 8 columns per lane in flight at a time: the loads do not wait on
+        // each other
+        for (int x0 = t; x0 < len; x0 += 8 * P) {
+            uint32_t v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int j = x0 + k * P - P;
+                v[k] = (j >= 1 && j <= n) ? clamp_code(hap[j - 1]) : (uint32_t)kPad;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (x0 + k * P < len) h[x0 + k * P] = (uint8_t)v[k];
         }
         hs = h;
         El = mine;
@@ -441,6 +515,17 @@ __device__ __forceinline__ void wait_vm0()
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// vmcnt(N) for N < 64: at most N vector memory operations of the wave
+// still outstanding
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt has 6 bits");
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(((N >> 4) << 14) | 0x0f70 | (N & 15));
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 __device__ __forceinline__ void wait_lgkm0()
 {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -521,19 +606,33 @@ __device__ __forceinline__ void adj_backward(const AdjPair<T, P, K> &pr, const T
     constexpr bool LDSPF = sizeof(T) == 4;
     constexpr bool PREFETCH = !LDSPF && PH_ADJ_PREFETCH;
     T cn[V];
+    // FP32: two LDS buffers, checkpoint q in buffer q & 1.  The copy of
+    // checkpoint q - 2 starts once the last block of checkpoint q has read
+    // its buffer, so every copy has the blocks of a whole checkpoint interval
+    // to arrive; at any block at most the copies of q and q - 1 are in
+    // flight, and vmcnt(V) (the V loads of the later one may remain) means
+    // that q's has landed.
+    auto ckbuf = [&](int q) { return (float *)pr.ckl + (q & 1) * V * 64; };
     if constexpr (LDSPF) {
         wait_vm0();  // the forward's checkpoint stores have completed
-        adj_stage_ck<K>((const float *)ck, (NB - 1) / R, pr.lane, (float *)pr.ckl);
+        const int q0 = (NB - 1) / R;
+        adj_stage_ck<K>((const float *)ck, q0, pr.lane, ckbuf(q0));
+        if (q0 > 0) adj_stage_ck<K>((const float *)ck, q0 - 1, pr.lane, ckbuf(q0 - 1));
     }
     if constexpr (PREFETCH) adj_load_ck<T, K>(ck, (NB - 1) / R, pr.lane, cn);
     for (int b = NB - 1; b >= 0; --b) {
         if constexpr (LDSPF) {
-            wait_vm0();
+            const int q = b / R;
+            if (q > 0)
+                wait_vm<V>();
+            else
+                wait_vm0();
+            const float *cb = ckbuf(q);
 #pragma unroll
-            for (int v = 0; v < V; ++v) cn[v] = pr.ckl[v * 64 + pr.lane];
-            if (b > 0 && (b - 1) / R != b / R) {
+            for (int v = 0; v < V; ++v) cn[v] = cb[v * 64 + pr.lane];
+            if (b == q * R && q >= 2) {
                 wait_lgkm0();  // the reads above have the buffer's values before it is refilled
-                adj_stage_ck<K>((const float *)ck, (b - 1) / R, pr.lane, (float *)pr.ckl);
+                adj_stage_ck<K>((const float *)ck, q - 2, pr.lane, ckbuf(q - 2));
             }
         } else if constexpr (!PREFETCH) {
             adj_load_ck<T, K>(ck, b / R, pr.lane, cn);
@@ -850,7 +949,7 @@ int adj_e_bytes(int P, int K)
 
 int adj64_e_bytes(int K) { return kCodes * K * AdjCfg<double, 64, 1>::ROW_BYTES; }
 
-int adj_ck_lds_bytes(int K) { return (3 * K + 3) * 64 * (int)sizeof(float); }
+int adj_ck_lds_bytes(int K) { return 2 * (3 * K + 3) * 64 * (int)sizeof(float); }
 
 static int occupancy(const void *fn, size_t lds)
 {
