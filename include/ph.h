@@ -125,11 +125,16 @@ void ph_plan_opts_default(ph_plan_opts *opts);
 
 /* Build a plan for problems of the given shape (HOST arrays, read once):
  * the partitioning of the pairs by read length into (lanes per pair, rows
- * per lane) configurations, each with its own work list (Section III-C),
- * and the scratch of the on-device sorting of a batch list into those lists
- * (Section III-A, stage 3).  This is the `ph_plan` call of the library's
- * call list, named ph_plan_create because C cannot give a function the name
- * of the ph_plan type.
+ * per lane) configurations, each with its own work list (Section III-C).
+ * The lists depend on the shape alone, so the plan builds them once, on the
+ * host, and uploads them: in configurations of 16 or more lanes a tile
+ * holds 64/lanes reads of one batch, each swept against a run of the
+ * batch's haplotypes one after the other (a chain); the remaining pairs
+ * form tiles of single pairs, longest haplotype first.  (The on-device
+ * sorting of a batch list into such lists, Section III-A stage 3, serves
+ * ph_forward_batch_noalloc, which has no plan.)  This is the `ph_plan` call
+ * of the library's call list, named ph_plan_create because C cannot give a
+ * function the name of the ph_plan type.
  * Validates the shape: batch ranges inside the read/haplotype counts, every
  * read and haplotype non-empty (PH_ERR_INVALID), every read at most 65535
  * bases (PH_ERR_UNSUPPORTED; plain mode: 1023); then sizes and allocates
@@ -161,9 +166,12 @@ ph_status ph_forward_batch(ph_plan *plan, const ph_problem *problem,
  * scratch (pair records, binning counters, FP64 queues, linear parameters)
  * is one fixed array of 7.5 MB inside the library, one copy per GPU,
  * held until the process ends.  Arguments as ph_forward_batch, with the
- * shape (HOST arrays, read during the call) in place of the plan; the same
- * values as a plan built with the library's own bin table (tune_table_path
- * NULL, force_p 0) and the default rescue threshold.
+ * shape (HOST arrays, read during the call) in place of the plan; the
+ * pairs of a plan built with the library's own bin table (tune_table_path
+ * NULL, force_p 0) and the default rescue threshold, each as a single pair
+ * (no chains): the same statuses, the same FP64 values, FP32 values to
+ * rounding (a chain groups the FP32 partial sums of the row-m sum by other
+ * column blocks).
  * Limits: at most 65536 pairs, 16384 batches, reads of 1..1023 bases, and
  * with log10_params at most 65536 read bases; larger problems give
  * PH_ERR_UNSUPPORTED before any device work.  Counts that differ between

@@ -212,6 +212,13 @@ struct ph_plan {
     std::vector<std::pair<int, int>> launch_order;  // FP32 stage: (bin, side stream) in launch order
     bool single = false;   // one persistent FP32 launch over all bins
     int single_grid = 0;
+    // binned mode: work lists built from the shape at plan creation, with
+    // chain tiles; the call copies the book image and writes the chain codes
+    std::vector<int64_t> bin_tiles;    // tiles per bin
+    int32_t chain_rec_base = 0;        // records of the lists; FP64 records of chain pairs follow
+    bool chain_tiles = false;
+    Book *d_book_img = nullptr;
+    uint8_t *d_chain_codes = nullptr;
 
     int64_t *d_out_offset = nullptr;
     int16_t *d_m2bin = nullptr;
@@ -291,6 +298,7 @@ void free_plan(ph_plan *p)
     if (p->adj_exec) (void)hipGraphExecDestroy(p->adj_exec);
     if (p->adj_graph) (void)hipGraphDestroy(p->adj_graph);
     void *bufs[] = {p->d_out_offset, p->d_m2bin, p->d_bin_G, p->d_hist, p->d_recs, p->d_book, p->d_bad, p->d_rescue, p->d_lin,
+                    p->d_book_img, p->d_chain_codes,
                     p->d_bnd32, p->d_bnd64, p->d_long_rescue,
                     p->d_adj_recs, p->d_ws, p->d_adj_ctr, p->d_q64, p->d_ws64, p->d_grad_pair, p->d_red};
     for (auto &e : p->ev_adj)
@@ -483,6 +491,121 @@ ph_status build_adjoint(ph_plan *p)
     return PH_OK;
 }
 
+// The FP32 work lists of a binned plan (Section III-C), built once from the
+// shape: records of every bin, bin b's range and tiles in the book image.
+// A bin's records are its chain tiles, longest chain first, then single
+// pairs, longest haplotype first.  A chain tile holds G = 64/P reads of one
+// batch and length bin, each against the same run of the batch's
+// haplotypes (at most kChainMaxHaps haplotypes and kChainMaxCols stream
+// columns, every haplotype after the first at least kChainMinHap long);
+// bins of fewer than 16 lanes and the reads of a batch's bin that do not
+// fill a tile take single pairs.  A haplotype-length split applies
+// to a chain tile by its stream length, to a single pair by its haplotype
+// length.
+void build_lists(ph_plan *p, const int32_t *rb, const int32_t *hb, const int64_t *ro, const int64_t *ho,
+                 const std::vector<int64_t> &out_off, const std::vector<int16_t> &m2bin,
+                 const std::vector<int16_t> &split, std::vector<PairRec> &recs, Book &img)
+{
+    const int nbins = (int)p->table.size();
+    auto binP = [&](int b) { return p->table[nbins - 1 - b].P; };
+    auto split_bin = [&](int b, int64_t len) {
+        return (split[b] < kBuckets && hap_bucket(len) >= split[b]) ? (int)split[kMaxBins + b] : b;
+    };
+    // chain tiles can place the FP64 record of a pair at chain_rec_base + out
+    const bool chains_ok = kChains && 2 * p->P < ((int64_t)1 << 31);
+    struct Tile {
+        int64_t len;   // sort key: stream or haplotype length
+        int64_t first; // into `pool`
+        int32_t count;
+    };
+    std::vector<std::vector<Tile>> chain_tiles(nbins), singles(nbins);
+    std::vector<PairRec> pool;
+    pool.reserve((size_t)p->P);
+    std::vector<std::pair<int, int32_t>> by_bin;
+    struct Seg {
+        int32_t h0, H;
+        int64_t len;
+    };
+    std::vector<Seg> segs;
+    for (int32_t q = 0; q < p->nb; ++q) {
+        const int32_t H = hb[q + 1] - hb[q];
+        if (H == 0) continue;
+        // runs of haplotypes for chains
+        segs.clear();
+        for (int32_t h = hb[q]; h < hb[q + 1]; ++h) {
+            const int64_t n = ho[h + 1] - ho[h];
+            if (!segs.empty() && n >= kChainMinHap && segs.back().H < kChainMaxHaps &&
+                segs.back().len + kChainSep + n <= kChainMaxCols) {
+                segs.back().H += 1;
+                segs.back().len += kChainSep + n;
+            } else {
+                segs.push_back(Seg{h, 1, n});
+            }
+        }
+        by_bin.clear();
+        for (int32_t r = rb[q]; r < rb[q + 1]; ++r) {
+            const int64_t m = ro[r + 1] - ro[r];
+            by_bin.push_back({m2bin[std::min<int64_t>(m, kMaxReadLen + 1)], r});
+        }
+        std::stable_sort(by_bin.begin(), by_bin.end(),
+                         [](const std::pair<int, int32_t> &a, const std::pair<int, int32_t> &b) { return a.first < b.first; });
+        auto out_of = [&](int32_t r, int32_t h) {
+            return (int32_t)(out_off[q] + (int64_t)(r - rb[q]) * H + (h - hb[q]));
+        };
+        auto add_single = [&](int b, int32_t r, int32_t h) {
+            const int64_t n = ho[h + 1] - ho[h];
+            const int bb = b == p->long_bin ? b : split_bin(b, n);
+            singles[bb].push_back(Tile{n, (int64_t)pool.size(), 1});
+            pool.push_back(PairRec{r, h, out_of(r, h), (int32_t)n});
+        };
+        size_t i = 0;
+        while (i < by_bin.size()) {
+            const int b = by_bin[i].first;
+            size_t e = i;
+            while (e < by_bin.size() && by_bin[e].first == b) ++e;
+            const int cnt = (int)(e - i);
+            for (const Seg &sg : segs) {
+                const int bb = b == p->long_bin ? b : split_bin(b, sg.len);
+                const int G = 64 / binP(bb);
+                const bool chain = chains_ok && b != p->long_bin && sg.H >= 2 && binP(bb) >= 16;
+                const int nt = chain ? cnt / G : 0;
+                for (int t = 0; t < nt; ++t) {
+                    chain_tiles[bb].push_back(Tile{sg.len, (int64_t)pool.size(), G});
+                    for (int g = 0; g < G; ++g) {
+                        const int32_t r = by_bin[i + (size_t)t * G + g].second;
+                        pool.push_back(PairRec{r, sg.h0, out_of(r, sg.h0), -sg.H});
+                    }
+                }
+                for (size_t k = i + (size_t)nt * G; k < e; ++k)
+                    for (int32_t h = sg.h0; h < sg.h0 + sg.H; ++h) add_single(b, by_bin[k].second, h);
+            }
+            i = e;
+        }
+    }
+    auto longest_first = [](const Tile &a, const Tile &b) { return a.len > b.len; };
+    recs.clear();
+    recs.reserve(pool.size());
+    p->bin_tiles.assign(nbins, 0);
+    p->chain_tiles = false;
+    int64_t tiles = 0;
+    for (int b = 0; b < nbins; ++b) {
+        std::stable_sort(chain_tiles[b].begin(), chain_tiles[b].end(), longest_first);
+        std::stable_sort(singles[b].begin(), singles[b].end(), longest_first);
+        img.bin_rec_begin[b] = (int32_t)recs.size();
+        img.bin_tile_begin[b] = (int32_t)tiles;
+        for (const Tile &t : chain_tiles[b])
+            for (int g = 0; g < t.count; ++g) recs.push_back(pool[(size_t)t.first + g]);
+        for (const Tile &t : singles[b]) recs.push_back(pool[(size_t)t.first]);
+        const int G = 64 / binP(b);
+        p->bin_tiles[b] = (int64_t)chain_tiles[b].size() + ((int64_t)singles[b].size() + G - 1) / G;
+        p->chain_tiles = p->chain_tiles || !chain_tiles[b].empty();
+        tiles += p->bin_tiles[b];
+    }
+    img.bin_rec_begin[nbins] = (int32_t)recs.size();
+    img.bin_tile_begin[nbins] = (int32_t)tiles;
+    p->chain_rec_base = (int32_t)recs.size();
+}
+
 }  // namespace
 
 extern "C" {
@@ -561,10 +684,6 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     } else {
         p->table = default_table(opts.force_p);
     }
-    HIPCHK(hipGetDevice(&p->device));
-    HIPCHK(hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device));
-    std::call_once(g_lut_once, [] { g_lut_status = upload_luts(); });
-    HIPCHK(g_lut_status);
     if (max_m > kMaxReadLen) {
         // the longest bin: 64 lanes x 16 rows per window, never tuned
         if (opts.plain) return fail(PH_ERR_UNSUPPORTED, "plain mode supports reads up to %d bases", kMaxReadLen);
@@ -628,11 +747,19 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
         p->split_at = (int)m2bin.size();
         m2bin.insert(m2bin.end(), split.begin(), split.end());
     }
+    Book img{};
+    std::vector<PairRec> recs;
+    if (!opts.plain) build_lists(p.get(), rb, hb, ro, ho, out_off, m2bin, split, recs, img);
+    // the first HIP calls (everything above is host work)
+    HIPCHK(hipGetDevice(&p->device));
+    HIPCHK(hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device));
+    std::call_once(g_lut_once, [] { g_lut_status = upload_luts(); });
+    HIPCHK(g_lut_status);
     p->bin_grid.assign(nbins, 0);
     for (int b = 0; b < nbins; ++b) {
-        if (!p->bin_pairs[b] || b == p->long_bin) continue;
+        if (opts.plain || !p->bin_pairs[b] || b == p->long_bin) continue;
         const TuneEntry &e = p->table[nbins - 1 - b];
-        const int64_t tiles = (p->bin_pairs[b] + binG[b] - 1) / binG[b];
+        const int64_t tiles = p->bin_tiles[b];
         const int64_t cap = (int64_t)p->cus * fwd32_blocks_per_cu(e.P, e.K);
         p->bin_grid[b] = (int)std::min<int64_t>(tiles, cap);
     }
@@ -658,7 +785,7 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
             if (!p->bin_pairs[b]) continue;
             const TuneEntry &e = p->table[nbins - 1 - b];
             ok = ok && single_supported(e.P, e.K);
-            tiles += (p->bin_pairs[b] + binG[b] - 1) / binG[b];
+            tiles += p->bin_tiles[b];
         }
         if (ok && tiles > 0) {
             p->single = true;
@@ -680,8 +807,18 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     if ((st = dalloc(&p->d_m2bin, m2bin.size()))) return st;
     if ((st = dalloc(&p->d_bin_G, kMaxBins))) return st;
     if ((st = dalloc(&p->d_hist, kMaxKeys))) return st;
-    if ((st = dalloc(&p->d_recs, std::max<int64_t>(P, 1)))) return st;
+    // binned: the lists' records, then (chain tiles) one FP64 record slot per pair
+    const int64_t nrecs = opts.plain ? P : (int64_t)recs.size() + (p->chain_tiles ? P : 0);
+    if ((st = dalloc(&p->d_recs, std::max<int64_t>(nrecs, 1)))) return st;
     if ((st = dalloc(&p->d_book, 1))) return st;
+    if (!opts.plain) {
+        if ((st = dalloc(&p->d_book_img, 1))) return st;
+        HIPCHK(hipMemcpy(p->d_book_img, &img, sizeof(Book), hipMemcpyHostToDevice));
+        if (!recs.empty())
+            HIPCHK(hipMemcpy(p->d_recs, recs.data(), recs.size() * sizeof(PairRec), hipMemcpyHostToDevice));
+        if (p->chain_tiles && (st = dalloc(&p->d_chain_codes, (size_t)(ho[nh] + (int64_t)kChainSep * nh))))
+            return st;
+    }
     if ((st = dalloc(&p->d_bad, 1))) return st;
     if ((st = dalloc(&p->d_rescue, (size_t)kRescueQueues * std::max<int64_t>(P, 1)))) return st;
     if (p->long_pairs) {
@@ -784,6 +921,9 @@ SweepArgs sweep_args(ph_plan *p, const ph_problem *pb, const double *lin, double
     a.long_bin = p->long_pairs ? p->long_bin : -1;
     a.bnd_stride = p->bnd_stride;
     a.long_rescue_list = p->d_long_rescue;
+    a.chain_codes = p->d_chain_codes;
+    a.chain_rec_base = p->chain_rec_base;
+    a.chain_recs = p->chain_tiles ? p->d_recs + p->chain_rec_base : nullptr;
     return a;
 }
 
@@ -798,14 +938,16 @@ ph_status enqueue_stage(ph_plan *p, int stage, const ph_problem *pb, const float
     sa.viterbi = viterbi ? 1 : 0;
     if (stage == 0) {
         if (log10_params) HIPCHK(launch_prep_params(log10_params, p->nread_bases, p->d_lin, s));
-        const BinArgs ba = bin_args(p, pb);
-        HIPCHK(launch_reset_keys(p->d_hist, ba.num_bins * kBuckets, p->d_book, s));
         if (p->opts.plain) {
+            const BinArgs ba = bin_args(p, pb);
+            HIPCHK(launch_reset_keys(p->d_hist, ba.num_bins * kBuckets, p->d_book, s));
             HIPCHK(launch_plain_records(ba, s));
         } else {
-            HIPCHK(launch_bin_count(ba, s));
-            HIPCHK(launch_bin_scan(ba, s));
-            HIPCHK(launch_bin_scatter(ba, s));
+            // the work lists come from plan creation: the book's bin ranges,
+            // zero cursors, and the chain code stream of this call's haplotypes
+            HIPCHK(launch_book_copy(p->d_book, p->d_book_img, s));
+            if (p->chain_tiles)
+                HIPCHK(launch_chain_codes(pb->hap_offset, pb->hap_bases, p->nh, p->d_chain_codes, s));
         }
     } else if (stage == 1) {
         if (p->opts.plain) {

@@ -39,9 +39,36 @@ constexpr int kMaxWindows = 64;
 constexpr int kMaxLongReadLen = kLongRows * kMaxWindows - 1;
 
 // One read/haplotype pair: indices into the problem and into the output.
+// In a chain tile of the FP32 sweep (n < 0) a record stands for the read
+// against the -n haplotypes hap, hap + 1, ... of its batch, whose outputs are
+// out, out + 1, ...
 struct PairRec {
     int32_t read, hap, out, n;
 };
+
+// Haplotype chains.  A lane group of 16 or more lanes sweeps its read against
+// several haplotypes of its batch one after the other, so that the wavefront
+// fills and drains once per chain instead of once per pair.  In the chain's
+// code stream every haplotype is followed by kChainSep PAD columns: the
+// absorbing row has its sum two columns past the haplotype end, and lane t
+// clears its states while it sweeps one of the last kChainSep - 2 of them,
+// kChainSep - 2 lanes per clearing step.  The stream of haplotype h starts at
+// hap_offset[h] + kChainSep h.
+#ifndef PH_CHAINS
+#define PH_CHAINS 1
+#endif
+constexpr bool kChains = PH_CHAINS;  // 0: single pairs only
+constexpr int kChainSep = 6;
+constexpr int kChainMaxHaps = 64;   // haplotype lengths of a chain sit one per lane
+// A group clears its lanes for one boundary at a time: the boundary of every
+// haplotype after a chain's first must come after the last lane of a 64-lane
+// group has cleared for the previous one, so those haplotypes have at least
+// 64 bases (shorter ones start a chain of their own).
+constexpr int kChainMinHap = 64;
+#ifndef PH_CHAIN_MAX_COLS
+#define PH_CHAIN_MAX_COLS 2048
+#endif
+constexpr int kChainMaxCols = PH_CHAIN_MAX_COLS;  // longest chain (columns and separators)
 
 struct DevProblem {
     const int64_t *read_offset;
@@ -119,6 +146,11 @@ struct SweepArgs {
     int64_t bnd_stride;          // elements per pair slot
     int32_t *long_rescue_list;   // FP64 queue of long pairs (record indices)
     int32_t viterbi;             // 1: max-product score (Viterbi) instead of the likelihood
+    // chain tiles: the code stream, and where the FP64 records of their
+    // pairs go (pair `out` of a chain at record chain_rec_base + out)
+    const uint8_t *chain_codes;
+    PairRec *chain_recs;
+    int32_t chain_rec_base;
 };
 
 // Adjoint: one record per pair, grouped by (P, K), longest haplotype first,
@@ -218,6 +250,11 @@ hipError_t launch_prep_params(const float *lg, int64_t npos, double *lin, hipStr
 hipError_t launch_validate(const DevProblem &pb, int64_t nread_bases, int64_t nhap_bases,
                            int32_t *bad, hipStream_t s);
 hipError_t launch_reset_keys(int32_t *hist, int nkeys, Book *book, hipStream_t s);
+// chain work lists built at plan creation: the plan's book image (bin ranges,
+// zero cursors) into the book, and the chain code stream of the call's haplotypes
+hipError_t launch_book_copy(Book *book, const Book *image, hipStream_t s);
+hipError_t launch_chain_codes(const int64_t *hap_offset, const uint8_t *hap_bases, int32_t num_haps,
+                              uint8_t *codes, hipStream_t s);
 hipError_t launch_na_setup(const int32_t *rb, const int32_t *hb, int32_t nb, int64_t *out_offset,
                            int16_t *m2bin, int32_t *bin_G, const BinTable &t, hipStream_t s);
 int fwd32_blocks_per_cu(int P, int K);

@@ -145,16 +145,17 @@ __device__ __forceinline__ void ring_load(uint32_t (&c)[RingPer<P>::N], int chun
     }
 }
 
+// (a chain's code stream holds codes 0..5 already: PAD stays PAD)
 template <int P>
 __device__ __forceinline__ void ring_store(uint16_t *ring, int chunk, const uint32_t (&c)[RingPer<P>::N], int t,
-                                           int code_bytes)
+                                           int code_bytes, bool coded = false)
 {
     constexpr int PER = RingPer<P>::N, CH = RingPer<P>::CH;
     const int slot = chunk & 3;
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
         const int x = t * PER + b;
-        const uint32_t code = c[b] == 0xffffu ? (uint32_t)kPad : clamp_code(c[b]);
+        const uint32_t code = c[b] == 0xffffu ? (uint32_t)kPad : coded ? c[b] : clamp_code(c[b]);
         const uint16_t off = (uint16_t)(code * code_bytes);
         ring[slot * CH + x] = off;
         if (slot == 0) ring[4 * CH + x] = off;
@@ -532,14 +533,35 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
         if (!__builtin_amdgcn_readfirstlane((int)gvalid)) return;
     }
     const bool fin = !W || m < r0 + kLongRows;  // this window holds row m + 1
-    const int n = gvalid ? rec.n : 0;
+    // Chain tile (FP32 binned sweep, records with n < 0): every group of the
+    // tile sweeps its read against the same NH haplotypes h0, h0 + 1, ... of
+    // its batch in turn, along their code stream; lane i holds the length of
+    // haplotype h0 + i, Lc is the stream's length up to the last haplotype's end.
+    constexpr bool CHN = kChains && HAT && !W && sizeof(T) == 4;
+    bool chain = false;
+    int NH = 1, h0 = 0, nvec = 0, Lc = 0;
+    if constexpr (CHN) {
+        const int r0n = __builtin_amdgcn_readfirstlane(rec.n);
+        chain = r0n < 0;
+        if (chain) {
+            NH = -r0n;
+            h0 = __builtin_amdgcn_readfirstlane(rec.hap);
+            if (lane < NH) nvec = (int)(pb.hap_offset[h0 + lane + 1] - pb.hap_offset[h0 + lane]);
+            int sum = nvec;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) sum += __shfl_xor(sum, off);
+            Lc = __builtin_amdgcn_readfirstlane(sum) + kChainSep * (NH - 1);
+        }
+    }
+    const int n = chain ? __builtin_amdgcn_readlane(nvec, 0) : gvalid ? rec.n : 0;
     const int64_t ho = gvalid ? pb.hap_offset[rec.hap] : 0;
-    const uint8_t *hap = pb.hap_bases + ho;
+    const uint8_t *hap = chain ? A.chain_codes + ho + (int64_t)kChainSep * h0 : pb.hap_bases + ho;
+    const int nring = chain ? Lc : n;  // columns of the ring's source
     T *bnd = W ? (T *)A.bnd + (int64_t)bnd_slot * A.bnd_stride : nullptr;
     T *top = (T *)(lds + C::E_BYTES + C::G * C::RING_BYTES);  // windowed: [3][64] staged boundary values
 
-    // the longest haplotype of the wave sets the number of steps
-    int nmax = n;
+    // the longest haplotype (chain) of the wave sets the number of steps
+    int nmax = nring;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) nmax = max(nmax, __shfl_xor(nmax, off));
     nmax = __builtin_amdgcn_readfirstlane(nmax);
@@ -563,6 +585,7 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     T al[K], be[K], de[K], ep[K], zt[K];  // plain states
     T ci[K], cd[K], ke[K];                // rescaled states (with ep)
     T edge = 0;
+    float e0f = 0.0f;   // FP32: the edge value times n (chains: divided by each haplotype's n)
     bool bad = false;  // rescaled states: one of my rows is outside what they carry
     bool phred32 = false;  // the FP32 sweep in Phred mode (rescaled states)
     if constexpr (HAT && sizeof(T) == 4) phred32 = lin == nullptr;
@@ -609,7 +632,10 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             ke[r] = inner ? k : 0.0f;
             ep[r] = real ? e : (i == m ? 1.0f : 0.0f);
         }
-        if (t == 0 && m > 0 && r0 == 0) edge = ldexpf(c_1mpf[gq[0]], kExp) / (float)n;
+        if (t == 0 && m > 0 && r0 == 0) {
+            e0f = ldexpf(c_1mpf[gq[0]], kExp);
+            edge = e0f / (float)n;
+        }
 #pragma unroll
         for (int q = 0; q < C::NPL; ++q) {
             float lm[C::RPP], lx[C::RPP];
@@ -684,7 +710,14 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
                 zt[r] = *slot(4, r);
             }
         }
-        if (t == 0 && m > 0 && r0 == 0) edge = (T)(ldexp(load_beta(pb, lin, ro, c_prob), kExp) / (double)n);
+        if (t == 0 && m > 0 && r0 == 0) {
+            if constexpr (sizeof(T) == 4) {
+                e0f = (float)ldexp(load_beta(pb, lin, ro, c_prob), kExp);
+                edge = e0f / (float)n;
+            } else {
+                edge = (T)(ldexp(load_beta(pb, lin, ro, c_prob), kExp) / (double)n);
+            }
+        }
         // E[c][row] = lam of the row against haplotype code c (N matches all,
         // PAD = 0); rescaled states: times alpha on the read's rows after the first
 #pragma unroll 1
@@ -741,10 +774,10 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     __syncthreads();
     {
         uint32_t c0[RingPer<P>::N], c1[RingPer<P>::N];
-        ring_load<P>(c0, 0, hap, n, t);
-        ring_load<P>(c1, 1, hap, n, t);
-        ring_store<P>(ring, 0, c0, t, C::CODE_BYTES);
-        ring_store<P>(ring, 1, c1, t, C::CODE_BYTES);
+        ring_load<P>(c0, 0, hap, nring, t);
+        ring_load<P>(c1, 1, hap, nring, t);
+        ring_store<P>(ring, 0, c0, t, C::CODE_BYTES, chain);
+        ring_store<P>(ring, 1, c1, t, C::CODE_BYTES, chain);
     }
     __syncthreads();
 
@@ -780,9 +813,65 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
     const int total = HAT ? (nmax + P + 2) & ~1 : (nmax + P) & ~1;
     const char *ebase_lane = E + lane * 8;
 
+    // Chain boundaries (wave-uniform).  Haplotype kc occupies stream
+    // positions cpos .. cpos + nk - 1; lane t sweeps position s - t at step s.
+    // At a boundary every lane clears its states before it sweeps a
+    // position in [bA, bA + CW), bA = cpos + nk + 2: the columns before are
+    // PAD, so M = I = 0 there in every real row (and every later M, I and D
+    // is then exactly 0 until the next haplotype), and the absorbing row's D
+    // holds the haplotype's whole sum, which the lane that holds it stores
+    // (raw, converted by the epilogue).  Clearing steps are even steps CW
+    // apart, each for the CW lanes whose window contains it; the first lane
+    // of a group also takes the next haplotype's edge value.
+    constexpr int CW = kChainSep - 2;
+    static_assert(CW >= 2 && CW % 2 == 0, "clearing steps fall on even steps");
+    int kc = 0, cpos = 0, nk = 0, bA = 0, rs_next = 0x7fffffff;
+    if (chain && NH > 1) {
+        nk = __builtin_amdgcn_readlane(nvec, 0);
+        bA = nk + 2;
+        rs_next = (bA + CW - 1) & ~1;
+    }
+    auto chain_clear = [&]() {
+        const int lo = rs_next - bA - CW, hi = rs_next - bA;
+        if (t > lo && t <= hi) {
+            if (rml >= 0 && rml < K) {
+                T dm = 0;
+#pragma unroll
+                for (int r = 0; r < K; ++r) dm = r == rml ? D[r] : dm;
+                if constexpr (V)
+                    acc = fmax(acc, (double)dm);
+                else
+                    acc += (double)dm;
+                A.out_log10[rec.out + kc] = acc;
+                acc = 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < K; ++r) D[r] = 0;
+            if (t == 0) {
+                const T ne = (T)(e0f / (float)__builtin_amdgcn_readlane(nvec, kc + 1));
+                if constexpr (P < 16) edge = ne;
+                Xd = ne;
+            }
+        }
+        if (hi >= P - 1) {
+            // every lane of the group is past this boundary
+            cpos += nk + kChainSep;
+            ++kc;
+            nk = __builtin_amdgcn_readlane(nvec, kc);
+            if (kc < NH - 1) {
+                bA = cpos + nk + 2;
+                rs_next = (bA + CW - 1) & ~1;
+            } else {
+                rs_next = 0x7fffffff;
+            }
+        } else {
+            rs_next += CW;
+        }
+    };
+
     for (int s0 = 0; s0 < total; s0 += CH) {
         uint32_t ahead[RingPer<P>::N];
-        ring_load<P>(ahead, s0 / CH + 2, hap, n, t);
+        ring_load<P>(ahead, s0 / CH + 2, hap, nring, t);
         if constexpr (W) {
             // lane t stages the boundary row at column s0 + 1 + t, which
             // lane 0 takes at step s0 + t (zero in window 0: the row-0
@@ -805,19 +894,31 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
         T la[C::KP], lb[C::KP];
         load_lam<T, P, K>(la, ebase_lane + hp[0]);
         if constexpr (HAT) {
-            for (int u = 0; u < cnt; u += 2) {
-                load_lam<T, P, K>(lb, ebase_lane + hp[u + 1]);
-                if constexpr (W) {
-                    window_step_hat<T, K, V>(M, I, D, Md, Id, Dd, la, ci, cd, ke, ep, edge, top, u, t, fin, bnd,
-                                             s0 + u, n);
-                    load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
-                    window_step_hat<T, K, V>(M, I, D, Md, Id, Dd, lb, ci, cd, ke, ep, edge, top, u + 1, t, fin,
-                                             bnd, s0 + u + 1, n);
-                } else {
-                    cell_step_hx<T, P, K, V>(M, I, D, Xd, la, ci, cd, ke, ep, cib, cdb, keb, edge, keep);
-                    load_lam<T, P, K>(la, ebase_lane + hp[u + 2]);
-                    cell_step_hx<T, P, K, V>(M, I, D, Xd, lb, ci, cd, ke, ep, cib, cdb, keb, edge, keep);
+            // the steps of the chunk, in runs that end at a chain's clearing
+            // steps (the run's loop has no branch of its own).  The ring reads
+            // go through a volatile pointer: merged into one 32-bit read they
+            // would be misaligned in every other lane.
+            const volatile __attribute__((address_space(3))) uint16_t *hv =
+                (const volatile __attribute__((address_space(3))) uint16_t *)hp;
+            int u = 0;
+            for (;;) {
+                const int stop = (CHN && rs_next - s0 < cnt) ? rs_next - s0 : cnt;
+                for (; u < stop; u += 2) {
+                    load_lam<T, P, K>(lb, ebase_lane + hv[u + 1]);
+                    if constexpr (W) {
+                        window_step_hat<T, K, V>(M, I, D, Md, Id, Dd, la, ci, cd, ke, ep, edge, top, u, t, fin, bnd,
+                                                 s0 + u, n);
+                        load_lam<T, P, K>(la, ebase_lane + hv[u + 2]);
+                        window_step_hat<T, K, V>(M, I, D, Md, Id, Dd, lb, ci, cd, ke, ep, edge, top, u + 1, t,
+                                                 fin, bnd, s0 + u + 1, n);
+                    } else {
+                        cell_step_hx<T, P, K, V>(M, I, D, Xd, la, ci, cd, ke, ep, cib, cdb, keb, edge, keep);
+                        load_lam<T, P, K>(la, ebase_lane + hv[u + 2]);
+                        cell_step_hx<T, P, K, V>(M, I, D, Xd, lb, ci, cd, ke, ep, cib, cdb, keb, edge, keep);
+                    }
                 }
+                if (u >= cnt) break;
+                if constexpr (CHN) chain_clear();
             }
             // the absorbing row's Dh (Viterbi: its running maximum) moves
             // into the FP64 accumulator; nothing else reads it
@@ -852,12 +953,41 @@ __device__ void sweep_tile(const SweepArgs &A, const int32_t *rec_idx_list, int 
             else
                 acc += (double)part;
         }
-        ring_store<P>(ring, s0 / CH + 2, ahead, t, C::CODE_BYTES);
+        ring_store<P>(ring, s0 / CH + 2, ahead, t, C::CODE_BYTES, chain);
         __syncthreads();
     }
 
     // ---- epilogue: the lane that holds the row-m sum writes it ---------------
     const bool owner = HAT ? (rml >= 0 && rml < K) : (t == P - 1);
+    if constexpr (CHN) {
+        if (chain) {
+            // the last haplotype's raw sum joins the others; then the group's
+            // lanes convert them, haplotype k in lane k mod P
+            if (owner) A.out_log10[rec.out + NH - 1] = acc;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const int cls = m < 128 ? 0 : m < 256 ? 1 : m < 512 ? 2 : 3;
+            for (int k = t; k < NH; k += P) {
+                const int out = rec.out + k;
+                const double sum = A.out_log10[out];
+                A.out_log10[out] = log10(sum) - (double)kExp * 0.30102999566398119521;
+                const bool ok = !gbad && (sum >= A.threshold) && (sum <= 3.0e38);
+                if (!ok) {
+                    // out of range: the rescaled FP64 sweep; a row outside the
+                    // rescaled states (or the max-product score): the plain one
+                    const int q = (gbad || V) ? kRescueClasses + cls : cls;
+                    const int hk = h0 + k;
+                    A.chain_recs[out] = PairRec{rec.read, hk, out, (int)(pb.hap_offset[hk + 1] - pb.hap_offset[hk])};
+                    const int slot = atomicAdd(&A.book->rescue_count[q], 1);
+                    A.rescue_list[q * A.rescue_stride + slot] = A.chain_rec_base + out;
+                    if (A.out_status) A.out_status[out] = 1;  // final value written by the FP64 sweep
+                } else if (A.out_status) {
+                    A.out_status[out] = 0;
+                }
+            }
+            return;
+        }
+    }
     if (gvalid && owner && fin) {
         const double lg = log10(acc) - (double)kExp * 0.30102999566398119521;
         const int cls = m < 128 ? 0 : m < 256 ? 1 : m < 512 ? 2 : 3;
@@ -1206,6 +1336,29 @@ __global__ __launch_bounds__(256) void k_bin_scatter(BinArgs a)
         if (key[j] >= 0) a.recs[base[key[j]] + rank[j]] = rec[j];
 }
 
+// The book of a plan whose work lists were built at plan creation: bin
+// ranges from the plan's image, every cursor and queue length zero.
+__global__ __launch_bounds__(256) void k_book_copy(Book *bk, const Book *img)
+{
+    int32_t *w = (int32_t *)bk;
+    const int32_t *r = (const int32_t *)img;
+    for (int i = threadIdx.x; i < (int)(sizeof(Book) / 4); i += 256) w[i] = r[i];
+}
+
+// Chain code stream: haplotype h at hap_offset[h] + kChainSep h, its base
+// codes (above 4: N) followed by kChainSep PAD codes.  One wave per haplotype.
+__global__ __launch_bounds__(256) void k_chain_codes(const int64_t *ho, const uint8_t *hb, int32_t nh,
+                                                     uint8_t *codes)
+{
+    const int lane = threadIdx.x & 63;
+    for (int h = blockIdx.x * 4 + (threadIdx.x >> 6); h < nh; h += gridDim.x * 4) {
+        const int64_t a = ho[h], n = ho[h + 1] - a;
+        uint8_t *dst = codes + a + (int64_t)kChainSep * h;
+        for (int64_t i = lane; i < n + kChainSep; i += 64)
+            dst[i] = i < n ? (uint8_t)clamp_code(hb[a + i]) : (uint8_t)kPad;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_plain_records(BinArgs a)
 {
     for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < a.num_pairs;
@@ -1280,6 +1433,20 @@ hipError_t launch_plain_records(const BinArgs &a, hipStream_t s)
 hipError_t launch_reset_keys(int32_t *hist, int nkeys, Book *book, hipStream_t s)
 {
     hipLaunchKernelGGL(k_reset, dim3(grid_for(nkeys, 256, 64)), dim3(256), 0, s, hist, nkeys, book);
+    return hipGetLastError();
+}
+
+hipError_t launch_book_copy(Book *book, const Book *image, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_book_copy, dim3(1), dim3(256), 0, s, book, image);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_codes(const int64_t *hap_offset, const uint8_t *hap_bases, int32_t num_haps,
+                              uint8_t *codes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_chain_codes, dim3(grid_for(num_haps, 4, 4096)), dim3(256), 0, s, hap_offset, hap_bases,
+                       num_haps, codes);
     return hipGetLastError();
 }
 

@@ -1,9 +1,11 @@
 """ph_forward_batch_noalloc, the forward that allocates nothing, against
 ph_forward_batch with a plan built on the same (built-in) bin table: the
-same values bit for bit and the same statuses, on two calls in a row that
-share the library's fixed scratch array, the second with a smaller input;
-both also against the FP64 oracle (FP32 pairs to 1e-3, FP64 pairs to
-1e-9)."""
+same statuses, FP64 values bit for bit and FP32 values to 1e-5 (a plan
+sweeps a read against several haplotypes as one chain, which groups the
+FP32 partial sums of the row-m sum differently from single pairs), on two
+calls in a row that share the library's fixed scratch array, the second
+with a smaller input; both also against the FP64 oracle (FP32 pairs to
+1e-3, FP64 pairs to 1e-9)."""
 import numpy as np
 import pytest
 
@@ -37,8 +39,11 @@ def _noalloc_forward(prob, log10_params=None):
 def _same(prob, a, b):
     (va, sa), (vb, sb) = a, b
     assert np.array_equal(sa, sb), np.nonzero(sa != sb)[0][:10]
-    diff = np.nonzero(va.view(np.int64) != vb.view(np.int64))[0]
+    f64 = (sa == binding.PAIR_FP64) | (sa == binding.PAIR_FP64_FLOOR)
+    diff = np.nonzero(f64 & (va.view(np.int64) != vb.view(np.int64)))[0]
     assert len(diff) == 0, (diff[:10], va[diff[:10]], vb[diff[:10]])
+    err = np.abs(va[~f64] - vb[~f64])
+    assert err.size == 0 or err.max() <= 1e-5, err.max()
 
 
 def test_noalloc_matches_plan_two_calls():
