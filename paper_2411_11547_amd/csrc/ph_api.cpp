@@ -197,7 +197,6 @@ struct ph_plan {
     int32_t max_m = 0, max_n = 0;
 
     std::vector<TuneEntry> table;      // bin b = table[table.size()-1-b] (longest first)
-    std::vector<int64_t> bin_pairs;    // pairs per bin (host count)
     std::vector<int> bin_grid;         // persistent grid per bin (0 = empty)
     int64_t class_pairs[kRescueClasses] = {0, 0, 0, 0};
     int rescue_grid[2][kRescueClasses] = {};  // [rescaled FP64, plain FP64] per class
@@ -499,10 +498,10 @@ ph_status build_adjoint(ph_plan *p)
 // haplotypes (at most kChainMaxHaps haplotypes and kChainMaxCols stream
 // columns, every haplotype after the first at least kChainMinHap long);
 // bins of fewer than 16 lanes and the reads of a batch's bin that do not
-// fill a tile take single pairs.  A haplotype-length split applies
-// to a chain tile by its stream length, to a single pair by its haplotype
-// length.
-void build_lists(ph_plan *p, const int32_t *rb, const int32_t *hb, const int64_t *ro, const int64_t *ho,
+// fill a tile take single pairs.  A haplotype-length split applies to
+// single pairs only (sending chains whose stream reaches the split length
+// to the split's bin was slower on the mixed batch).
+bool build_lists(ph_plan *p, const int32_t *rb, const int32_t *hb, const int64_t *ro, const int64_t *ho,
                  const std::vector<int64_t> &out_off, const std::vector<int16_t> &m2bin,
                  const std::vector<int16_t> &split, std::vector<PairRec> &recs, Book &img)
 {
@@ -564,13 +563,12 @@ void build_lists(ph_plan *p, const int32_t *rb, const int32_t *hb, const int64_t
             size_t e = i;
             while (e < by_bin.size() && by_bin[e].first == b) ++e;
             const int cnt = (int)(e - i);
+            const int G = 64 / binP(b);
             for (const Seg &sg : segs) {
-                const int bb = b == p->long_bin ? b : split_bin(b, sg.len);
-                const int G = 64 / binP(bb);
-                const bool chain = chains_ok && b != p->long_bin && sg.H >= 2 && binP(bb) >= 16;
+                const bool chain = chains_ok && b != p->long_bin && sg.H >= 2 && binP(b) >= 16;
                 const int nt = chain ? cnt / G : 0;
                 for (int t = 0; t < nt; ++t) {
-                    chain_tiles[bb].push_back(Tile{sg.len, (int64_t)pool.size(), G});
+                    chain_tiles[b].push_back(Tile{sg.len, (int64_t)pool.size(), G});
                     for (int g = 0; g < G; ++g) {
                         const int32_t r = by_bin[i + (size_t)t * G + g].second;
                         pool.push_back(PairRec{r, sg.h0, out_of(r, sg.h0), -sg.H});
@@ -604,6 +602,19 @@ void build_lists(ph_plan *p, const int32_t *rb, const int32_t *hb, const int64_t
     img.bin_rec_begin[nbins] = (int32_t)recs.size();
     img.bin_tile_begin[nbins] = (int32_t)tiles;
     p->chain_rec_base = (int32_t)recs.size();
+    // every pair exactly once
+    std::vector<uint8_t> seen((size_t)p->P, 0);
+    for (const PairRec &r : recs) {
+        const int32_t cnt = r.n < 0 ? -r.n : 1;
+        for (int32_t k = 0; k < cnt; ++k) {
+            const int64_t o = (int64_t)r.out + k;
+            if (o < 0 || o >= p->P || seen[(size_t)o]) return false;
+            seen[(size_t)o] = 1;
+        }
+    }
+    for (uint8_t v : seen)
+        if (!v) return false;
+    return true;
 }
 
 }  // namespace
@@ -714,7 +725,6 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
         split[kMaxBins + b] = (int16_t)(e.n_split ? b - 1 : b);
         any_split = any_split || e.n_split;
     }
-    p->bin_pairs.assign(nbins, 0);
     int64_t cells = 0;
     for (int32_t q = 0; q < nb; ++q) {
         const int64_t H = hb[q + 1] - hb[q];
@@ -723,14 +733,6 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
         for (int32_t r = rb[q]; r < rb[q + 1]; ++r) {
             const int m = (int)(ro[r + 1] - ro[r]);
             const int bin = m2bin[std::min(m, kMaxReadLen + 1)];
-            if (split[bin] < kBuckets) {
-                int64_t over = 0;
-                for (int32_t h = hb[q]; h < hb[q + 1]; ++h) over += hap_bucket(ho[h + 1] - ho[h]) >= split[bin];
-                p->bin_pairs[bin] += H - over;
-                p->bin_pairs[split[kMaxBins + bin]] += over;
-            } else {
-                p->bin_pairs[bin] += H;
-            }
             cells += (int64_t)m * nsum;
             if (bin == p->long_bin) {  // every pair of the long bin gets a boundary slot
                 p->long_pairs += H;
@@ -749,7 +751,8 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     }
     Book img{};
     std::vector<PairRec> recs;
-    if (!opts.plain) build_lists(p.get(), rb, hb, ro, ho, out_off, m2bin, split, recs, img);
+    if (!opts.plain && !build_lists(p.get(), rb, hb, ro, ho, out_off, m2bin, split, recs, img))
+        return fail(PH_ERR_INVALID, "internal: the work lists do not cover every pair once");
     // the first HIP calls (everything above is host work)
     HIPCHK(hipGetDevice(&p->device));
     HIPCHK(hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device));
@@ -757,7 +760,9 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     HIPCHK(g_lut_status);
     p->bin_grid.assign(nbins, 0);
     for (int b = 0; b < nbins; ++b) {
-        if (opts.plain || !p->bin_pairs[b] || b == p->long_bin) continue;
+        // (a chain tile can sit in a split's second bin although no single
+        // pair's haplotype reaches the split: bins are launched by tiles)
+        if (opts.plain || !p->bin_tiles[b] || b == p->long_bin) continue;
         const TuneEntry &e = p->table[nbins - 1 - b];
         const int64_t tiles = p->bin_tiles[b];
         const int64_t cap = (int64_t)p->cus * fwd32_blocks_per_cu(e.P, e.K);
@@ -782,7 +787,7 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
         bool ok = true;
         int64_t tiles = 0;
         for (int b = 0; b < nbins; ++b) {
-            if (!p->bin_pairs[b]) continue;
+            if (!p->bin_tiles[b]) continue;
             const TuneEntry &e = p->table[nbins - 1 - b];
             ok = ok && single_supported(e.P, e.K);
             tiles += p->bin_tiles[b];

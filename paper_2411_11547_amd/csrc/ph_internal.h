@@ -66,7 +66,7 @@ constexpr int kChainMaxHaps = 64;   // haplotype lengths of a chain sit one per 
 // 64 bases (shorter ones start a chain of their own).
 constexpr int kChainMinHap = 64;
 #ifndef PH_CHAIN_MAX_COLS
-#define PH_CHAIN_MAX_COLS 2048
+#define PH_CHAIN_MAX_COLS 4096
 #endif
 constexpr int kChainMaxCols = PH_CHAIN_MAX_COLS;  // longest chain (columns and separators)
 

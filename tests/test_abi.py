@@ -186,3 +186,28 @@ def test_tune_table_validation(tmp_path):
             assert "table" not in msg and "split" not in msg, (text, msg)
         else:
             assert st in (-1, -2) and err in msg, (text, st, msg)
+
+
+def test_work_lists_cover_every_pair(tmp_path):
+    """The FP32 work lists a binned plan builds on the host (chains of a
+    batch's haplotypes per read, single pairs) cover every pair exactly once;
+    plan creation checks that before its first HIP call, so on a host without
+    a GPU it fails there and not on the lists.  Mixed and ragged shapes, with
+    the built-in table, a table whose split sends chains to a second bin, and
+    every forced group size."""
+    rng = np.random.default_rng(5)
+    probs = [wl.config2(regions=30), wl.config1(regions=3)]
+    batches = []
+    for q in range(12):
+        ms = rng.integers(1, 1100, size=int(rng.integers(0, 12)))
+        ns = rng.choice([1, 5, 40, 63, 64, 65, 100, 300, 700, 1500, 2100], size=int(rng.integers(0, 9)))
+        batches.append(([("A" * int(m)) for m in ms], [("C" * int(n)) for n in ns]))
+    probs.append(wl.from_strings(batches))
+    split = tmp_path / "split.txt"
+    split.write_text("223 16 14\n255 16 16 256 32 8\n1023 64 16\n")
+    for prob in probs:
+        for kw in (dict(), dict(tune_table_path=str(split).encode()), dict(force_p=16), dict(force_p=32),
+                   dict(force_p=64)):
+            st, msg = _plan_status(prob, **kw)
+            assert "work lists" not in msg, (kw, msg)
+            assert st == -4 or st == 0, (kw, st, msg)
