@@ -38,12 +38,12 @@ def _kernels(db):
                        "lds_size, scratch_size from kernels order by start").fetchall()
 
 
-def _spans(rows, start_marker, members):
+def _spans(rows, start_markers, members):
     """Span (ms) from the first to the last dispatch of `members` after each
-    dispatch whose name contains `start_marker`."""
+    dispatch whose name contains one of `start_markers`."""
     spans, lo, hi = [], None, None
     for name, s, e, *_ in rows:
-        if start_marker in name:
+        if any(mk in name for mk in start_markers):
             if lo is not None:
                 spans.append((hi - lo) / 1e6)
             lo = hi = None
@@ -69,9 +69,12 @@ def kernels(db):
               f"{lds:>6} {scr:>7}")
     fwd = [r for r in rows if not any(k in r[0] for k in SWEEP) or _is_sweep(r[0])]
     vit = [r for r in rows if not any(k in r[0] for k in SWEEP) or not _is_sweep(r[0])]
-    for title, rs, marker, members in (("FP32 sweep stage of the forward calls", fwd, "k_reset", SWEEP),
-                                       ("FP32 sweep stage of the Viterbi calls", vit, "k_reset", SWEEP),
-                                       ("adjoint kernels", rows, "k_zero_i32", ADJ)):
+    # a forward call starts with its binning (k_reset) or, with work lists
+    # built at plan creation, with the copy of the plan's book (k_book_copy)
+    first = ("k_reset", "k_book_copy")
+    for title, rs, marker, members in (("FP32 sweep stage of the forward calls", fwd, first, SWEEP),
+                                       ("FP32 sweep stage of the Viterbi calls", vit, first, SWEEP),
+                                       ("adjoint kernels", rows, ("k_zero_i32",), ADJ)):
         sp = [x for x in _spans(rs, marker, members) if x > 0]
         if not sp:
             continue
