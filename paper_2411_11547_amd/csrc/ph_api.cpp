@@ -490,12 +490,19 @@ ph_status build_adjoint(ph_plan *p)
     return PH_OK;
 }
 
+// Longer chains make fewer, longer tiles, whose last round runs on part of
+// the GPU: a plan halves the chain length (down to 1,024 columns) until it
+// has this many chain tiles, 8 per wave of a launch of 3 waves per SIMD on
+// 256 CUs.  (The mixed batch keeps 4,096 columns; the uniform batch, one bin
+// of 64,000 reads against 8 haplotypes, gets 2,048.)
+constexpr int64_t kChainMinTiles = 24576;
+
 // The FP32 work lists of a binned plan (Section III-C), built once from the
 // shape: records of every bin, bin b's range and tiles in the book image.
 // A bin's records are its chain tiles, longest chain first, then single
 // pairs, longest haplotype first.  A chain tile holds G = 64/P reads of one
 // batch and length bin, each against the same run of the batch's
-// haplotypes (at most kChainMaxHaps haplotypes and kChainMaxCols stream
+// haplotypes (at most kChainMaxHaps haplotypes and max_cols stream
 // columns, every haplotype after the first at least kChainMinHap long);
 // bins of fewer than 16 lanes and the reads of a batch's bin that do not
 // fill a tile take single pairs.  A haplotype-length split applies to
@@ -503,7 +510,8 @@ ph_status build_adjoint(ph_plan *p)
 // to the split's bin was slower on the mixed batch).
 bool build_lists(ph_plan *p, const int32_t *rb, const int32_t *hb, const int64_t *ro, const int64_t *ho,
                  const std::vector<int64_t> &out_off, const std::vector<int16_t> &m2bin,
-                 const std::vector<int16_t> &split, std::vector<PairRec> &recs, Book &img)
+                 const std::vector<int16_t> &split, int max_cols, std::vector<PairRec> &recs, Book &img,
+                 int64_t &chain_tile_count)
 {
     const int nbins = (int)p->table.size();
     auto binP = [&](int b) { return p->table[nbins - 1 - b].P; };
@@ -534,7 +542,7 @@ bool build_lists(ph_plan *p, const int32_t *rb, const int32_t *hb, const int64_t
         for (int32_t h = hb[q]; h < hb[q + 1]; ++h) {
             const int64_t n = ho[h + 1] - ho[h];
             if (!segs.empty() && n >= kChainMinHap && segs.back().H < kChainMaxHaps &&
-                segs.back().len + kChainSep + n <= kChainMaxCols) {
+                segs.back().len + kChainSep + n <= max_cols) {
                 segs.back().H += 1;
                 segs.back().len += kChainSep + n;
             } else {
@@ -585,6 +593,7 @@ bool build_lists(ph_plan *p, const int32_t *rb, const int32_t *hb, const int64_t
     recs.reserve(pool.size());
     p->bin_tiles.assign(nbins, 0);
     p->chain_tiles = false;
+    chain_tile_count = 0;
     int64_t tiles = 0;
     for (int b = 0; b < nbins; ++b) {
         std::stable_sort(chain_tiles[b].begin(), chain_tiles[b].end(), longest_first);
@@ -597,6 +606,7 @@ bool build_lists(ph_plan *p, const int32_t *rb, const int32_t *hb, const int64_t
         const int G = 64 / binP(b);
         p->bin_tiles[b] = (int64_t)chain_tiles[b].size() + ((int64_t)singles[b].size() + G - 1) / G;
         p->chain_tiles = p->chain_tiles || !chain_tiles[b].empty();
+        chain_tile_count += (int64_t)chain_tiles[b].size();
         tiles += p->bin_tiles[b];
     }
     img.bin_rec_begin[nbins] = (int32_t)recs.size();
@@ -751,8 +761,15 @@ ph_status ph_plan_create(const ph_shape *shape, const ph_plan_opts *opts_in, ph_
     }
     Book img{};
     std::vector<PairRec> recs;
-    if (!opts.plain && !build_lists(p.get(), rb, hb, ro, ho, out_off, m2bin, split, recs, img))
-        return fail(PH_ERR_INVALID, "internal: the work lists do not cover every pair once");
+    if (!opts.plain) {
+        // the longest chains that still leave kChainMinTiles chain tiles (or 1,024 columns)
+        for (int cols = kChainMaxCols;; cols /= 2) {
+            int64_t nchain = 0;
+            if (!build_lists(p.get(), rb, hb, ro, ho, out_off, m2bin, split, cols, recs, img, nchain))
+                return fail(PH_ERR_INVALID, "internal: the work lists do not cover every pair once");
+            if (nchain == 0 || nchain >= kChainMinTiles || cols <= 1024) break;
+        }
+    }
     // the first HIP calls (everything above is host work)
     HIPCHK(hipGetDevice(&p->device));
     HIPCHK(hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device));
