@@ -145,3 +145,76 @@ def test_measured_traffic_needs_matching_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("w2") is None
     prof.write_text("traffic_bytes_per_launch: 1.5e9\nworkload: w1\nforward_sources_sha256: 00\n")
     assert bench.measured_traffic("w1") is None
+
+
+def _chain_clearing_schedule(P, ns, sep=6, chunk=None):
+    """The clearing schedule of a chain tile, step by step as the FP32 sweep
+    keeps it (wave-uniform bookkeeping, runs of steps in ring chunks): for
+    each (lane, haplotype boundary) the step at which the lane clears."""
+    cw = sep - 2
+    chunk = chunk or (64 if P == 64 else 32)
+    H = len(ns)
+    total = (sum(ns) + sep * (H - 1) + P + 2) & ~1
+    st = dict(kc=0, cpos=0, nk=0, bA=0, rs=1 << 31)
+    if H > 1:
+        st.update(nk=ns[0], bA=ns[0] + 2, rs=(ns[0] + 2 + cw - 1) & ~1)
+    clears = {}
+
+    def clear(step):
+        assert step == st["rs"], "a clearing step fell behind the sweep"
+        lo, hi = st["rs"] - st["bA"] - cw, st["rs"] - st["bA"]
+        for t in range(max(lo + 1, 0), min(hi, P - 1) + 1):
+            assert (t, st["kc"]) not in clears
+            clears[(t, st["kc"])] = step
+        if hi >= P - 1:
+            st["cpos"] += st["nk"] + sep
+            st["kc"] += 1
+            st["nk"] = ns[st["kc"]]
+            if st["kc"] < H - 1:
+                st["bA"] = st["cpos"] + st["nk"] + 2
+                st["rs"] = (st["bA"] + cw - 1) & ~1
+            else:
+                st["rs"] = 1 << 31
+        else:
+            st["rs"] += cw
+
+    for s0 in range(0, total, chunk):
+        cnt = min(chunk, total - s0)
+        u = 0
+        while True:
+            stop = min(st["rs"] - s0, cnt)
+            u = max(u, stop if stop > u else u)
+            if u >= cnt:
+                break
+            clear(s0 + u)
+    return clears
+
+
+def test_chain_clearing_schedule():
+    """Every lane of a chain tile clears its states exactly once per
+    haplotype boundary, at a step where it sweeps one of the four separator
+    columns from the third on (the absorbing row's sum is complete and every
+    state of the real rows is zero from there), for every group size and
+    haplotypes of 64 bases or more after the first (the plan's rule); and
+    the schedule breaks when a later haplotype is much shorter than a
+    64-lane group."""
+    rng = np.random.default_rng(1)
+    for P in (4, 8, 16, 32, 64):
+        for _ in range(400):
+            H = int(rng.integers(2, 9))
+            ns = [int(rng.integers(1, 400))] + [int(rng.integers(64, 400)) for _ in range(H - 1)]
+            clears = _chain_clearing_schedule(P, ns)
+            assert len(clears) == P * (H - 1)
+            cpos = 0
+            for k in range(H - 1):
+                first_sep = cpos + ns[k]
+                for t in range(P):
+                    pos = clears[(t, k)] - t
+                    assert first_sep + 2 <= pos < first_sep + 6, (P, ns, k, t, pos)
+                cpos += ns[k] + 6
+    try:
+        _chain_clearing_schedule(64, [300, 20, 300])
+    except AssertionError:
+        pass
+    else:
+        raise AssertionError("a 20-base haplotype inside a 64-lane chain went unnoticed")
