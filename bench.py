@@ -126,7 +126,7 @@ def time_forward(plan, dev, steps, warmup, stage=True):
 ADJ_FLOPS_PER_CELL = 37  # 11 recompute + 11 adjoint + 15 gradient accumulation (FP32)
 
 
-def time_pipeline(prob, subsets=8, steps=2):
+def time_pipeline(prob, subsets=3, steps=2):
     """Host-input streaming forward (the paper's workflow, Section III-A):
     pinned host arrays in, scores on the host out, H2D of the next subset
     overlapped with the current subset's compute.  Not the headline value:

@@ -248,7 +248,7 @@ void ph_plan_destroy(ph_plan *plan);
  * copies are staged by the runtime. */
 typedef struct {
     int64_t max_subset_cells; /* cells (sum of m*n) per subset; a larger batch forms a
-                                 subset of its own; <= 0 selects 2e10 */
+                                 subset of its own; <= 0 selects 6e10 */
     int32_t buffer_sets;      /* device input/output buffer sets, reused in turn; 0: one per
                                  subset when all of them take at most a quarter of the free
                                  device memory (then no copy waits for compute), else 2;

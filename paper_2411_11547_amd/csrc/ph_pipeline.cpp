@@ -9,7 +9,9 @@
 // Streams: H2D copies on `h2d`, plans on `comp[k % 2]`, D2H copies on
 // `d2h`.  Two compute streams let the start of subset k+1 (binning and the
 // first bins' sweeps) overlap the tail of subset k (44.3 -> 41.4 ms per call
-// on the mixed batch in 9 subsets).  When every subset's inputs and outputs
+// on the mixed batch in 9 subsets).  Subsets of up to 6e10 cells by default:
+// with haplotype chains, whose tiles are longer, the mixed batch runs in 4
+// subsets at 36.4-36.9 ms per call against 39.1-39.4 in 9.  When every subset's inputs and outputs
 // together take at most a
 // quarter of the free device memory (or the caller asks for as many buffer
 // sets as there are subsets), each subset gets its own buffer set and
@@ -46,6 +48,7 @@ void set_last_error(const char *msg);  // ph_api.cpp: the message of ph_last_err
 namespace {
 
 constexpr int kCompStreams = PH_PIPE_COMP_STREAMS;  // subsets alternate between these
+constexpr int64_t kDefaultSubsetCells = 60000000000LL;  // cells per subset unless given
 
 ph_status pfail(ph_status st, const char *fmt, ...)
 {
@@ -158,7 +161,7 @@ ph_status ph_pipeline_create(const ph_shape *shape, const ph_pipeline_opts *opts
     *out = nullptr;
     ph_pipeline_opts opts;
     if (opts_in) opts = *opts_in; else ph_pipeline_opts_default(&opts);
-    const int64_t cap = opts.max_subset_cells > 0 ? opts.max_subset_cells : (int64_t)20000000000LL;
+    const int64_t cap = opts.max_subset_cells > 0 ? opts.max_subset_cells : kDefaultSubsetCells;
     const int32_t nb = shape->num_batches, nr = shape->num_reads, nh = shape->num_haps;
     if (nb < 0 || nr < 0 || nh < 0) return pfail(PH_ERR_INVALID, "negative counts");
     if ((nb > 0 && (!shape->batch_read_begin || !shape->batch_hap_begin)) || !shape->read_offset ||
